@@ -1,0 +1,212 @@
+/*
+ * fastlbp — loopy belief propagation on binary factor graphs with local-structure factors,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "FastLBP: GPU-Accelerated Belief Propagation for Program Analysis" (arXiv 2509.22337).
+ *   - The factor graph and the messages are those of Section 3.1-3.2: variable-to-factor
+ *     messages Eq.(1), factor-to-variable messages Eq.(2), marginals Eq.(3).
+ *   - Factors have local structure (Section 3.3, Eq.(4)): every factor type below is evaluated in
+ *     O(degree) instead of enumerating 2^degree assignments.
+ *   - An update strategy is a preorder over the edges (Section 4.2.1, Definition 2), given here as
+ *     an integer rank per edge: equal ranks form one class, lower ranks are updated first within
+ *     an iteration. FLOODING is the all-parallel strategy (PARALL of Table 1), RANKED covers the
+ *     fixed sequential order (SEQFIX: distinct ranks), topological orders (TOPO) and ordered
+ *     groups. A dependency analysis (Algorithm 2, Section 4.2.3) splits the ranked strategy into
+ *     levels that are updated in parallel (Theorem 2).
+ *
+ * Conventions
+ *   Variables are binary. Factors are given in factor-major CSR: factor a owns edges
+ *   [factor_offsets[a], factor_offsets[a+1]); the HEAD of a factor is its LAST edge and the edges
+ *   before it are its inputs x_1..x_n.
+ *   Factor types:
+ *     FASTLBP_PRIOR     degree 1; f(1) = p, f(0) = 1-p with p = factor_params[a].
+ *     FASTLBP_AND       degree >= 2; f = [y = x_1 & ... & x_n].
+ *     FASTLBP_OR        degree >= 2; f = [y = x_1 | ... | x_n].
+ *     FASTLBP_NOT       degree 2;    f = [y = !x_1].
+ *     FASTLBP_IMPLIES   degree >= 2; probabilistic Horn rule p: x_1 & ... & x_n -> y (Section 1,
+ *                       Section 2.2): f = p if all inputs are 1 and y = 1, 1-p if all inputs are 1
+ *                       and y = 0, 1 otherwise. p = factor_params[a] (1 = hard implication;
+ *                       factor_params == NULL means p = 1).
+ *     FASTLBP_NOISY_OR  degree >= 2; P(y = 0 | x) = (1 - leak) * prod_{j: x_j = 1} (1 - p_j),
+ *                       leak = factor_params[a] in [0,1), p_j = edge_params[e] of input edge e.
+ *   Readings where the paper is silent: messages start uniform; every stored message is
+ *   normalised; a computed message whose two entries are both 0 is replaced by the uniform message
+ *   and counted in fastlbp_run_stats.contradictions; damping mixes normalised old and new
+ *   messages, stored = lambda*old + (1-lambda)*new; the residual of an iteration is the largest
+ *   change of P(x=1) over the messages written in it; a run stops after the first iteration whose
+ *   residual is below tol (tol = 0: run max_iters iterations).
+ *
+ * Ownership and threading
+ *   The caller owns every input array; the library copies what it needs before returning, so the
+ *   arrays may be freed afterwards. Output arrays are caller-allocated host memory. A graph handle
+ *   is not thread-safe; distinct handles are independent. All device work of a handle runs on the
+ *   stream given in fastlbp_options (or on a stream the library creates); calls that return host
+ *   results synchronise that stream.
+ *
+ * Errors
+ *   Every int-returning call returns FASTLBP_OK (0) or a negative FASTLBP_E_* code, and
+ *   fastlbp_last_error() then describes the failure (thread-local, valid until the next call on
+ *   the same thread). A failed call leaves the handle as it was. Non-convergence and
+ *   contradictions are not errors; they are reported in fastlbp_run_stats.
+ */
+#ifndef FASTLBP_H
+#define FASTLBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FASTLBP_OK = 0,
+    FASTLBP_E_INVALID_ARG = -1, /* NULL pointer, bad enum value, bad size, bad damping/tol */
+    FASTLBP_E_BAD_GRAPH = -2,   /* malformed CSR, variable id out of range, duplicate variable in a
+                                   factor, wrong arity, parameter outside [0,1] or NaN */
+    FASTLBP_E_BAD_SCHEDULE = -3,/* rank array missing for FASTLBP_SCHED_RANKED */
+    FASTLBP_E_OOM = -4,         /* device allocation failed */
+    FASTLBP_E_DEVICE = -5,      /* no usable gfx950 device, or a HIP call failed */
+    FASTLBP_E_TOO_LARGE = -6,   /* graph exceeds a documented limit (edges >= 2^31, factor degree
+                                   > FASTLBP_MAX_DEGREE) or a server's memory budget */
+    FASTLBP_E_STATE = -7        /* call not valid in the handle's state (e.g. run before a schedule) */
+};
+
+enum { FASTLBP_PRIOR = 0, FASTLBP_AND = 1, FASTLBP_OR = 2, FASTLBP_NOT = 3, FASTLBP_IMPLIES = 4,
+       FASTLBP_NOISY_OR = 5 };
+
+/* Message precision. FP64: messages stored as float64 log-likelihood ratios, factor algebra in
+ * linear float64. FP32: messages stored as float32 log-likelihood ratios and the factor algebra in
+ * the float32 log domain; beliefs, the convergence residual and marginals stay float64. */
+enum { FASTLBP_FP64 = 0, FASTLBP_FP32 = 1 };
+
+enum { FASTLBP_SCHED_FLOODING = 0, FASTLBP_SCHED_RANKED = 1 };
+
+/* Executor. LEVELS: one kernel launch per level and phase over the whole GPU (wide levels,
+ * flooding). PERSISTENT: one workgroup runs every level and iteration of the run in a single
+ * launch with workgroup barriers between phases (narrow levels, small graphs). AUTO picks by the
+ * width of the levels. Both give the same messages up to floating-point rounding order. */
+enum { FASTLBP_EXEC_AUTO = 0, FASTLBP_EXEC_LEVELS = 1, FASTLBP_EXEC_PERSISTENT = 2 };
+
+#define FASTLBP_MAX_DEGREE 16385 /* largest factor degree (inputs + head) */
+
+typedef struct fastlbp_options {
+    int32_t precision;  /* FASTLBP_FP64 or FASTLBP_FP32 */
+    int32_t device;     /* HIP device ordinal */
+    void *stream;       /* hipStream_t to enqueue on; NULL = the library creates one */
+    int32_t executor;   /* FASTLBP_EXEC_* */
+    int32_t use_graph;  /* 1 = replay iterations from a captured hipGraph, 0 = plain launches */
+    /* Optional device allocator (e.g. a framework's caching allocator). Both NULL = hipMalloc /
+     * hipFree. alloc returns NULL on failure. */
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *alloc_ctx;
+} fastlbp_options;
+
+/* Fills *o with defaults: FP64, device 0, library stream, AUTO executor, graphs on, hipMalloc. */
+void fastlbp_options_default(fastlbp_options *o);
+
+typedef struct fastlbp_run_stats {
+    int32_t iterations;          /* iterations executed by the last fastlbp_run */
+    int32_t converged;           /* 1 if the last iteration's residual was below tol */
+    double residual;             /* residual of the last iteration */
+    int64_t contradictions;      /* messages replaced by uniform during the run */
+    int32_t levels;              /* levels per iteration (dependency analysis) */
+    int32_t executor;            /* FASTLBP_EXEC_LEVELS or FASTLBP_EXEC_PERSISTENT */
+    double algorithmic_bytes_per_iter; /* bytes an iteration must move at minimum (see design notes) */
+    double device_ms;            /* device time of the run, HIP events on the handle's stream */
+    int64_t message_updates;     /* factor-to-variable updates performed (edges x iterations) */
+} fastlbp_run_stats;
+
+typedef struct fastlbp_graph *fastlbp_graph_t;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Graph (Section 3.1; the Initialization stage of Section 4.1)                                 */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Creates a graph: validates the CSR, builds the variable-major transpose, folds PRIOR factors
+ * into per-variable potentials, buckets factors by degree and uploads everything to the device.
+ *   num_vars, num_factors  sizes (>= 0)
+ *   factor_offsets [F+1]   non-decreasing, factor_offsets[0] = 0, E = factor_offsets[F] < 2^31
+ *   edge_vars [E]          variable of each edge, in [0, num_vars), no variable twice per factor
+ *   factor_types [F]       FASTLBP_PRIOR .. FASTLBP_NOISY_OR
+ *   factor_params [F]      per type as above; may be NULL (PRIOR then defaults to 0.5, IMPLIES to 1)
+ *   edge_params [E]        NOISY_OR activation of each input edge; may be NULL (then 1)
+ * The schedule starts as FLOODING with uniform messages and no evidence.
+ * Errors: E_INVALID_ARG, E_BAD_GRAPH, E_TOO_LARGE, E_OOM, E_DEVICE. */
+int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                         const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
+                         const double *edge_params, const fastlbp_options *opts, fastlbp_graph_t *out);
+
+void fastlbp_graph_destroy(fastlbp_graph_t g);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Update strategy and dependency analysis (Section 4.2, Definition 2, Algorithm 2)             */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Sets the update strategy. kind = FASTLBP_SCHED_FLOODING ignores edge_rank; RANKED requires
+ * edge_rank [E] (any int32 values; equal ranks = one equivalence class of the preorder). Runs the
+ * dependency analysis: edges are ordered by (rank, edge id); a rank class joins the current level
+ * unless one of its edges has a neighbour of Definition 1 in that level, in which case the class
+ * starts a new level (Algorithm 2 with cuts only between classes, which coincides with the
+ * printed algorithm on total orders). PRIOR edges take part in the analysis like any edge.
+ * *num_levels_out (may be NULL) receives the number of levels. Errors: E_INVALID_ARG,
+ * E_BAD_SCHEDULE, E_OOM, E_DEVICE. */
+int fastlbp_schedule_set(fastlbp_graph_t g, int32_t kind, const int32_t *edge_rank, int32_t *num_levels_out);
+
+/* Copies the level of every edge [E] (0-based) of the current schedule. */
+int fastlbp_schedule_levels(fastlbp_graph_t g, int32_t *level_of_edge);
+
+/* Host-only dependency analysis with no device and no graph handle, for callers that only need
+ * the levels. Same inputs and result as fastlbp_graph_create + fastlbp_schedule_set(RANKED) +
+ * fastlbp_schedule_levels. factor_types may be NULL. Errors: E_INVALID_ARG, E_BAD_GRAPH. */
+int fastlbp_analyze_levels(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                           const int32_t *edge_vars, const int32_t *edge_rank, int32_t *level_of_edge,
+                           int32_t *num_levels_out);
+
+/* Host-only validation of a graph (the checks of fastlbp_graph_create, no device needed). */
+int fastlbp_graph_validate(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                           const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
+                           const double *edge_params);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Evidence (the feedback loop of Section 5.2.2) and messages                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Clamps (values 0/1) or releases (value -1) n variables. Messages are kept, so the next run
+ * starts warm from the current state. Errors: E_INVALID_ARG. */
+int fastlbp_evidence_set(fastlbp_graph_t g, int32_t n, const int32_t *vars, const int8_t *values);
+
+/* Releases every clamp. */
+int fastlbp_evidence_clear(fastlbp_graph_t g);
+
+/* Runs belief propagation: at most max_iters iterations of the current schedule from the current
+ * message state, stopping early when an iteration's residual is below tol (tol = 0: never).
+ * damping lambda in [0,1). stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
+int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
+
+/* Marginals P(X_v = 1) [V] of Eq.(3) from the current messages, evidence and priors (float64).
+ * A variable whose incoming messages contradict (all products 0) gets 0.5. */
+int fastlbp_marginals(fastlbp_graph_t g, double *p1);
+
+/* Current factor-to-variable messages as P(x_v = 1) [E] (PRIOR edges report their prior). */
+int fastlbp_messages_get(fastlbp_graph_t g, double *f2v_p1);
+
+/* Sets the factor-to-variable messages from P(x_v = 1) [E] in [0,1] (PRIOR entries ignored).
+ * Serves checkpoint/restore, warm start and one-step parity checks. Errors: E_INVALID_ARG. */
+int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1);
+
+/* Resets every message to uniform (cold start). */
+int fastlbp_messages_reset(fastlbp_graph_t g);
+
+/* Description of the last failure on this thread ("" if none). */
+const char *fastlbp_last_error(void);
+
+/* Library version string. */
+const char *fastlbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTLBP_H */

@@ -1,0 +1,299 @@
+"""MI355X-native loopy belief propagation with local-structure factors (FastLBP, arXiv 2509.22337).
+
+The compute path is libfastlbp.so (hand-written HIP for gfx950 behind a C ABI declared in
+include/fastlbp.h). This module only marshals arguments: numpy arrays in, numpy arrays out, with
+PyTorch supplying the HIP stream and (optionally) the device caching allocator. There is no CPU
+fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+from typing import Optional
+
+import numpy as np
+
+from .workloads import AND, IMPLIES, NOISY_OR, NOT, OR, PRIOR  # noqa: F401  (factor tags)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastlbp.so")
+
+OK, E_INVALID_ARG, E_BAD_GRAPH, E_BAD_SCHEDULE, E_OOM, E_DEVICE, E_TOO_LARGE, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32 = 0, 1
+SCHED_FLOODING, SCHED_RANKED = 0, 1
+EXEC_AUTO, EXEC_LEVELS, EXEC_PERSISTENT = 0, 1, 2
+MAX_DEGREE = 16385
+
+_ERR_NAMES = {E_INVALID_ARG: "E_INVALID_ARG", E_BAD_GRAPH: "E_BAD_GRAPH", E_BAD_SCHEDULE: "E_BAD_SCHEDULE",
+              E_OOM: "E_OOM", E_DEVICE: "E_DEVICE", E_TOO_LARGE: "E_TOO_LARGE", E_STATE: "E_STATE"}
+
+
+class FastLBPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("executor", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("alloc", _ALLOC_FN),
+                ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("contradictions", ctypes.c_int64), ("levels", ctypes.c_int32), ("executor", ctypes.c_int32),
+                ("algorithmic_bytes_per_iter", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("message_updates", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = [
+    "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_destroy", "fastlbp_schedule_set",
+    "fastlbp_schedule_levels", "fastlbp_analyze_levels", "fastlbp_graph_validate", "fastlbp_evidence_set",
+    "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
+    "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version",
+]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libfastlbp.so (built by ``paper_2509_22337_amd.build``). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FastLBPError(E_DEVICE, f"{LIB_PATH} is not built; run paper_2509_22337_amd.build.build()")
+    # PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7) as the system one
+    # the library links against. Loading PyTorch first makes the dynamic loader bind the library to
+    # that already-loaded runtime, so streams and allocations are shared by one runtime instead of
+    # two runtimes living side by side in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.fastlbp_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.fastlbp_options_default.restype = None
+    lib.fastlbp_graph_create.argtypes = [i32, i32, P, P, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.fastlbp_graph_destroy.argtypes = [P]
+    lib.fastlbp_graph_destroy.restype = None
+    lib.fastlbp_schedule_set.argtypes = [P, i32, P, ctypes.POINTER(i32)]
+    lib.fastlbp_schedule_levels.argtypes = [P, P]
+    lib.fastlbp_analyze_levels.argtypes = [i32, i32, P, P, P, P, ctypes.POINTER(i32)]
+    lib.fastlbp_graph_validate.argtypes = [i32, i32, P, P, P, P, P]
+    lib.fastlbp_evidence_set.argtypes = [P, i32, P, P]
+    lib.fastlbp_evidence_clear.argtypes = [P]
+    lib.fastlbp_run.argtypes = [P, i32, f64, f64, ctypes.POINTER(RunStats)]
+    lib.fastlbp_marginals.argtypes = [P, P]
+    lib.fastlbp_messages_get.argtypes = [P, P]
+    lib.fastlbp_messages_set.argtypes = [P, P]
+    lib.fastlbp_messages_reset.argtypes = [P]
+    lib.fastlbp_last_error.argtypes = []
+    lib.fastlbp_last_error.restype = ctypes.c_char_p
+    lib.fastlbp_version.argtypes = []
+    lib.fastlbp_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("fastlbp_options_default", "fastlbp_graph_destroy", "fastlbp_last_error", "fastlbp_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FastLBPError(rc, load().fastlbp_last_error().decode())
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _arrays(fac_off, edge_var, fac_type, fac_param=None, edge_param=None):
+    fac_off = np.ascontiguousarray(fac_off, dtype=np.int64)
+    edge_var = np.ascontiguousarray(edge_var, dtype=np.int32)
+    fac_type = np.ascontiguousarray(fac_type, dtype=np.uint8)
+    fac_param = None if fac_param is None else np.ascontiguousarray(fac_param, dtype=np.float64)
+    edge_param = None if edge_param is None else np.ascontiguousarray(edge_param, dtype=np.float64)
+    return fac_off, edge_var, fac_type, fac_param, edge_param
+
+
+def validate(num_vars, fac_off, edge_var, fac_type, fac_param=None, edge_param=None) -> None:
+    """Host-only graph validation (raises FastLBPError)."""
+    fo, ev, ft, fp, ep = _arrays(fac_off, edge_var, fac_type, fac_param, edge_param)
+    _check(load().fastlbp_graph_validate(int(num_vars), len(ft), _p(fo), _p(ev), _p(ft), _p(fp), _p(ep)))
+
+
+def analyze_levels(num_vars, fac_off, edge_var, edge_rank) -> tuple[np.ndarray, int]:
+    """Host-only dependency analysis: level of every edge and the number of levels."""
+    fo = np.ascontiguousarray(fac_off, dtype=np.int64)
+    ev = np.ascontiguousarray(edge_var, dtype=np.int32)
+    rk = None if edge_rank is None else np.ascontiguousarray(edge_rank, dtype=np.int32)
+    out = np.zeros(len(ev), dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(load().fastlbp_analyze_levels(int(num_vars), len(fo) - 1, _p(fo), _p(ev), _p(rk), _p(out), ctypes.byref(n)))
+    return out, int(n.value)
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through PyTorch's caching allocator."""
+
+    def __init__(self, device: int, stream):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+        self.alloc_cb = _ALLOC_FN(self._alloc)
+        self.free_cb = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+        except Exception:
+            return None
+
+    def _free(self, ptr, ctx):
+        if ptr:
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_LIVE: "weakref.WeakSet[Graph]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device memory while PyTorch (which may own the allocator) is still alive
+    for g in list(_LIVE):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A factor graph resident on one GPU (see include/fastlbp.h for the semantics of every call)."""
+
+    def __init__(self, num_vars, fac_off, edge_var, fac_type, fac_param=None, edge_param=None, precision="fp64",
+                 executor="auto", device: int = 0, use_graph: bool = True, allocator: str = "torch", stream=None):
+        lib = load()
+        self._h = None
+        fo, ev, ft, fp, ep = _arrays(fac_off, edge_var, fac_type, fac_param, edge_param)
+        self.num_vars = int(num_vars)
+        self.num_edges = len(ev)
+        self.fac_type = ft
+        self.fac_off = fo
+        o = Options()
+        lib.fastlbp_options_default(ctypes.byref(o))
+        o.precision = {"fp64": FP64, "fp32": FP32}[precision]
+        o.executor = {"auto": EXEC_AUTO, "levels": EXEC_LEVELS, "persistent": EXEC_PERSISTENT}[executor]
+        o.device = int(device)
+        o.use_graph = 1 if use_graph else 0
+        self._keep = []
+        self.stream = None
+        try:
+            import torch
+            if torch.cuda.is_available():
+                self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+                o.stream = ctypes.c_void_p(self.stream.cuda_stream)
+                if allocator == "torch":
+                    ta = _TorchAllocator(device, self.stream)
+                    self._keep.append(ta)
+                    o.alloc = ta.alloc_cb
+                    o.free = ta.free_cb
+        except ImportError:
+            pass
+        h = ctypes.c_void_p()
+        _check(lib.fastlbp_graph_create(self.num_vars, len(ft), _p(fo), _p(ev), _p(ft), _p(fp), _p(ep),
+                                        ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+        _LIVE.add(self)
+
+    @classmethod
+    def from_workload(cls, w, **kw) -> "Graph":
+        g = cls(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, **kw)
+        if w.edge_rank is not None:
+            g.schedule_set(SCHED_RANKED, w.edge_rank)
+        if w.evidence is not None:
+            g.evidence_array(w.evidence)
+        return g
+
+    def close(self):
+        if self._h is not None:
+            load().fastlbp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def schedule_set(self, kind: int, edge_rank=None) -> int:
+        rk = None if edge_rank is None else np.ascontiguousarray(edge_rank, dtype=np.int32)
+        if rk is not None and len(rk) != self.num_edges:
+            raise FastLBPError(E_INVALID_ARG, "edge_rank must have one entry per edge")
+        n = ctypes.c_int32(0)
+        _check(load().fastlbp_schedule_set(self._h, int(kind), _p(rk), ctypes.byref(n)))
+        return int(n.value)
+
+    def schedule_levels(self) -> np.ndarray:
+        out = np.zeros(self.num_edges, dtype=np.int32)
+        _check(load().fastlbp_schedule_levels(self._h, _p(out)))
+        return out
+
+    def evidence_set(self, vars_, values):
+        v = np.ascontiguousarray(vars_, dtype=np.int32)
+        x = np.ascontiguousarray(values, dtype=np.int8)
+        if len(v) != len(x):
+            raise FastLBPError(E_INVALID_ARG, "vars and values differ in length")
+        _check(load().fastlbp_evidence_set(self._h, len(v), _p(v), _p(x)))
+
+    def evidence_array(self, ev):
+        """Sets the full evidence vector (-1 / 0 / 1 per variable)."""
+        ev = np.asarray(ev, dtype=np.int8)
+        self.evidence_set(np.arange(len(ev), dtype=np.int32), ev)
+
+    def evidence_clear(self):
+        _check(load().fastlbp_evidence_clear(self._h))
+
+    def run(self, max_iters: int, tol: float = 0.0, damping: float = 0.0) -> dict:
+        st = RunStats()
+        _check(load().fastlbp_run(self._h, int(max_iters), float(tol), float(damping), ctypes.byref(st)))
+        return st.as_dict()
+
+    def marginals(self) -> np.ndarray:
+        out = np.zeros(self.num_vars)
+        _check(load().fastlbp_marginals(self._h, _p(out)))
+        return out
+
+    def messages_get(self) -> np.ndarray:
+        out = np.zeros(self.num_edges)
+        _check(load().fastlbp_messages_get(self._h, _p(out)))
+        return out
+
+    def messages_set(self, p1):
+        a = np.ascontiguousarray(p1, dtype=np.float64)
+        if len(a) != self.num_edges:
+            raise FastLBPError(E_INVALID_ARG, "one message per edge")
+        _check(load().fastlbp_messages_set(self._h, _p(a)))
+
+    def messages_reset(self):
+        _check(load().fastlbp_messages_reset(self._h))

@@ -1,0 +1,69 @@
+// Host-side graph preparation: validation, variable-major transpose, prior folding, the
+// dependency analysis (Algorithm 2) and per-level work lists. No device code here.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.h"
+
+namespace fastlbp {
+
+void set_error(const std::string &msg);
+void clear_error();
+
+int validate_graph(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const uint8_t *fac_type,
+                   const double *fac_param, const double *edge_param);
+
+// Class-atomic Algorithm 2 over the preorder given by `rank` (nullptr = one class).
+// level[e] receives the level of every edge; returns the number of levels.
+int32_t analyze_levels(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const int32_t *rank,
+                       std::vector<int32_t> &level);
+
+struct HostGraph {
+    int32_t V = 0, F = 0;
+    int64_t E = 0;
+    std::vector<int64_t> fac_off;
+    std::vector<int32_t> edge_var;
+    std::vector<uint8_t> fac_type;
+    std::vector<double> fac_param;   // defaults applied
+    std::vector<double> edge_param;  // defaults applied
+    std::vector<int32_t> edge_fac;
+    std::vector<int32_t> var_off;    // [V+1] non-PRIOR edges
+    std::vector<int32_t> var_edge;
+    std::vector<int32_t> var_deg;    // non-PRIOR degree
+    // PRIOR factors folded per variable: finite LLR sum (bits) and counts of p = 1 / p = 0
+    std::vector<double> prior_fin;
+    std::vector<int32_t> prior_pos, prior_neg;
+    std::vector<int8_t> evidence;    // -1, 0, 1
+    int32_t max_deg = 0;
+    int64_t nonprior_edges = 0;
+
+    void build(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
+               const double *ep);
+    void phi(std::vector<Belief> &out) const;
+};
+
+// Work lists for one schedule. Levels without any non-PRIOR edge are not executed.
+struct HostPlan {
+    int32_t num_levels = 0;       // levels of the dependency analysis (all edges)
+    int32_t exec_levels = 0;      // levels with work on the device
+    int32_t all_active = 0;
+    int32_t max_level_edges = 0;  // widest executed level (active non-PRIOR edges)
+    std::vector<int32_t> level_of_edge;
+    std::vector<int32_t> edge_exec_level;  // [E], -1 for PRIOR
+    std::vector<int32_t> fac_list[FB_COUNT];
+    std::vector<int32_t> fac_lvl_off[FB_COUNT];
+    std::vector<int32_t> var_list[VB_COUNT];
+    std::vector<int32_t> var_lvl_off[VB_COUNT];
+    std::vector<int32_t> init_var[VB_COUNT];
+    double bytes_per_iter = 0.0;   // algorithmic bytes of one iteration
+    int64_t updates_per_iter = 0;  // non-PRIOR edges written per iteration
+
+    void build(const HostGraph &g, const std::vector<int32_t> &level, int32_t nlevels, bool flooding,
+               int msg_bytes, int param_bytes);
+};
+
+int factor_bucket(int deg);
+
+}  // namespace fastlbp

@@ -1,0 +1,370 @@
+// Host-side graph preparation (the Initialization and Dependency Analysis stages of Section 4.1).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "fastlbp.h"
+#include "host.h"
+
+namespace fastlbp {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace fastlbp
+
+extern "C" const char *fastlbp_last_error(void) { return fastlbp::g_last_error.c_str(); }
+
+namespace fastlbp {
+
+static bool bad_prob(double p) { return !(p >= 0.0 && p <= 1.0); }
+
+int validate_graph(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
+                   const double *ep) {
+    if (V < 0 || F < 0) {
+        set_error("negative size");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (!off || (F > 0 && !ft)) {
+        set_error("factor_offsets and factor_types are required");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (off[0] != 0) {
+        set_error("factor_offsets[0] must be 0");
+        return FASTLBP_E_BAD_GRAPH;
+    }
+    for (int32_t a = 0; a < F; ++a)
+        if (off[a + 1] < off[a]) {
+            set_error("factor_offsets must be non-decreasing (factor " + std::to_string(a) + ")");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    int64_t E = off[F];
+    if (E >= (int64_t(1) << 31)) {
+        set_error("more than 2^31-1 edges");
+        return FASTLBP_E_TOO_LARGE;
+    }
+    if (E > 0 && !ev) {
+        set_error("edge_vars is required");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    for (int64_t e = 0; e < E; ++e)
+        if (ev[e] < 0 || ev[e] >= V) {
+            set_error("edge " + std::to_string(e) + " has variable id out of range");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    std::vector<int32_t> seen(V > 0 ? V : 1, -1);
+    for (int32_t a = 0; a < F; ++a) {
+        int64_t d = off[a + 1] - off[a];
+        int t = ft[a];
+        std::string where = " (factor " + std::to_string(a) + ")";
+        if (t > FASTLBP_NOISY_OR) {
+            set_error("unknown factor type" + where);
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        if (t == FASTLBP_PRIOR && d != 1) {
+            set_error("PRIOR needs degree 1" + where);
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        if (t == FASTLBP_NOT && d != 2) {
+            set_error("NOT needs degree 2" + where);
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        if (t != FASTLBP_PRIOR && t != FASTLBP_NOT && d < 2) {
+            set_error("AND/OR/IMPLIES/NOISY_OR need degree >= 2" + where);
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        if (d > FASTLBP_MAX_DEGREE) {
+            set_error("factor degree above FASTLBP_MAX_DEGREE" + where);
+            return FASTLBP_E_TOO_LARGE;
+        }
+        for (int64_t e = off[a]; e < off[a + 1]; ++e) {
+            if (seen[ev[e]] == a) {
+                set_error("variable " + std::to_string(ev[e]) + " appears twice" + where);
+                return FASTLBP_E_BAD_GRAPH;
+            }
+            seen[ev[e]] = a;
+        }
+        if (fp) {
+            double p = fp[a];
+            if ((t == FASTLBP_PRIOR || t == FASTLBP_IMPLIES) && bad_prob(p)) {
+                set_error("parameter outside [0,1]" + where);
+                return FASTLBP_E_BAD_GRAPH;
+            }
+            if (t == FASTLBP_NOISY_OR && !(p >= 0.0 && p < 1.0)) {
+                set_error("noisy-or leak outside [0,1)" + where);
+                return FASTLBP_E_BAD_GRAPH;
+            }
+        }
+        if (ep && t == FASTLBP_NOISY_OR)
+            for (int64_t e = off[a]; e + 1 < off[a + 1]; ++e)
+                if (bad_prob(ep[e])) {
+                    set_error("noisy-or activation outside [0,1]" + where);
+                    return FASTLBP_E_BAD_GRAPH;
+                }
+    }
+    return FASTLBP_OK;
+}
+
+// Class-atomic Algorithm 2. Edges are visited in (rank, edge id) order, one rank class at a time.
+// A class joins the current level unless one of its edges e = (a, v) has a neighbour of
+// Definition 1 in the level: an edge (a*, v*) with v* adjacent to a, v* != v and a* != a. Such a
+// neighbour precedes e strictly (it belongs to an earlier class), so the class opens a new level.
+// Per variable we remember whether the current level holds an edge at it and from which factor
+// (or "several"), which makes the test O(degree of a) per factor touched by the class.
+int32_t analyze_levels(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const int32_t *rank,
+                       std::vector<int32_t> &level) {
+    int64_t E = off[F];
+    level.assign(E, 0);
+    if (E == 0) return 0;
+    if (!rank) return 1;
+    std::vector<int32_t> edge_fac(E);
+    for (int32_t a = 0; a < F; ++a)
+        for (int64_t e = off[a]; e < off[a + 1]; ++e) edge_fac[e] = a;
+    std::vector<int32_t> order(E);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return rank[x] < rank[y]; });
+    std::vector<int32_t> mark_level(V, -1), mark_fac(V, -1);
+    int32_t cur = 0;
+    bool first = true;
+    int64_t i = 0;
+    while (i < E) {
+        int64_t j = i;
+        while (j < E && rank[order[j]] == rank[order[i]]) ++j;
+        bool cut = false;
+        if (!first) {
+            // factors of the class are contiguous runs because ids ascend inside a class
+            int64_t k = i;
+            while (k < j && !cut) {
+                int32_t a = edge_fac[order[k]];
+                int64_t k2 = k;
+                while (k2 < j && edge_fac[order[k2]] == a) ++k2;
+                int32_t only_v = (k2 - k == 1) ? ev[order[k]] : -1;
+                for (int64_t q = off[a]; q < off[a + 1]; ++q) {
+                    int32_t vs = ev[q];
+                    if (vs == only_v) continue;
+                    if (mark_level[vs] == cur && mark_fac[vs] != a) {
+                        cut = true;
+                        break;
+                    }
+                }
+                k = k2;
+            }
+        }
+        if (cut) ++cur;
+        first = false;
+        for (int64_t k = i; k < j; ++k) {
+            int32_t e = order[k];
+            int32_t v = ev[e], a = edge_fac[e];
+            level[e] = cur;
+            if (mark_level[v] != cur) {
+                mark_level[v] = cur;
+                mark_fac[v] = a;
+            } else if (mark_fac[v] != a) {
+                mark_fac[v] = -2;
+            }
+        }
+        i = j;
+    }
+    return cur + 1;
+}
+
+void HostGraph::build(int32_t V_, int32_t F_, const int64_t *off, const int32_t *ev, const uint8_t *ft,
+                      const double *fp, const double *ep) {
+    V = V_;
+    F = F_;
+    E = off[F];
+    fac_off.assign(off, off + F + 1);
+    edge_var.assign(ev, ev + E);
+    fac_type.assign(ft, ft + F);
+    fac_param.resize(F);
+    edge_param.assign(E, 0.0);
+    edge_fac.resize(E);
+    max_deg = 0;
+    for (int32_t a = 0; a < F; ++a) {
+        int t = ft[a];
+        double def = (t == FASTLBP_PRIOR) ? 0.5 : (t == FASTLBP_IMPLIES ? 1.0 : 0.0);
+        fac_param[a] = fp ? fp[a] : def;
+        for (int64_t e = off[a]; e < off[a + 1]; ++e) {
+            edge_fac[e] = a;
+            if (t == FASTLBP_NOISY_OR && e + 1 < off[a + 1]) edge_param[e] = ep ? ep[e] : 1.0;
+        }
+        if (t != FASTLBP_PRIOR) max_deg = std::max<int32_t>(max_deg, int32_t(off[a + 1] - off[a]));
+    }
+    // variable-major transpose of the non-PRIOR edges (stable: ascending edge id per variable)
+    var_off.assign(V + 1, 0);
+    nonprior_edges = 0;
+    for (int64_t e = 0; e < E; ++e)
+        if (fac_type[edge_fac[e]] != FASTLBP_PRIOR) {
+            var_off[ev[e] + 1]++;
+            ++nonprior_edges;
+        }
+    for (int32_t v = 0; v < V; ++v) var_off[v + 1] += var_off[v];
+    var_edge.resize(nonprior_edges);
+    std::vector<int32_t> fill(var_off.begin(), var_off.end() - 1);
+    for (int64_t e = 0; e < E; ++e)
+        if (fac_type[edge_fac[e]] != FASTLBP_PRIOR) var_edge[fill[ev[e]]++] = int32_t(e);
+    var_deg.resize(V);
+    for (int32_t v = 0; v < V; ++v) var_deg[v] = var_off[v + 1] - var_off[v];
+    // PRIOR folding: LLR in bits, p = 1 and p = 0 become infinite terms
+    prior_fin.assign(V, 0.0);
+    prior_pos.assign(V, 0);
+    prior_neg.assign(V, 0);
+    for (int32_t a = 0; a < F; ++a)
+        if (fac_type[a] == FASTLBP_PRIOR) {
+            int32_t v = ev[off[a]];
+            double p = fac_param[a];
+            if (p >= 1.0)
+                prior_pos[v]++;
+            else if (p <= 0.0)
+                prior_neg[v]++;
+            else
+                prior_fin[v] += std::log2(p) - std::log2(1.0 - p);
+        }
+    evidence.assign(V, -1);
+}
+
+void HostGraph::phi(std::vector<Belief> &out) const {
+    out.resize(V);
+    for (int32_t v = 0; v < V; ++v) {
+        Belief b;
+        b.fin = prior_fin[v];
+        b.npos = prior_pos[v] + (evidence[v] == 1 ? 1 : 0);
+        b.nneg = prior_neg[v] + (evidence[v] == 0 ? 1 : 0);
+        out[v] = b;
+    }
+}
+
+int factor_bucket(int deg) {
+    if (deg <= kThreadMaxDeg) return FB_THREAD;
+    if (deg <= kWaveMaxDeg) return FB_WAVE;
+    return FB_BLOCK;
+}
+
+void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int32_t nlevels, bool flooding,
+                     int msg_bytes, int param_bytes) {
+    num_levels = nlevels;
+    level_of_edge = level;
+    all_active = flooding ? 1 : 0;
+    // executed levels: those holding at least one non-PRIOR edge
+    std::vector<int32_t> exec_of(std::max(nlevels, 1), -1);
+    std::vector<int64_t> level_np(std::max(nlevels, 1), 0);
+    for (int64_t e = 0; e < g.E; ++e)
+        if (g.fac_type[g.edge_fac[e]] != FASTLBP_PRIOR) level_np[level[e]]++;
+    exec_levels = 0;
+    max_level_edges = 0;
+    for (int32_t L = 0; L < nlevels; ++L)
+        if (level_np[L] > 0) {
+            exec_of[L] = exec_levels++;
+            max_level_edges = std::max<int32_t>(max_level_edges, int32_t(level_np[L]));
+        }
+    edge_exec_level.assign(g.E, -1);
+    for (int64_t e = 0; e < g.E; ++e)
+        if (g.fac_type[g.edge_fac[e]] != FASTLBP_PRIOR) edge_exec_level[e] = exec_of[level[e]];
+    // factor tasks per executed level: a factor joins level L if one of its edges is active in L
+    std::vector<std::vector<int32_t>> fac_by_level(FB_COUNT * std::max(exec_levels, 1));
+    std::vector<std::vector<int32_t>> var_by_level(VB_COUNT * std::max(exec_levels, 1));
+    bytes_per_iter = 0.0;
+    updates_per_iter = 0;
+    for (int32_t a = 0; a < g.F; ++a) {
+        if (g.fac_type[a] == FASTLBP_PRIOR) continue;
+        int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
+        int bucket = factor_bucket(int(d));
+        int32_t prev = -1;
+        // levels of a factor's edges in ascending order of level, each level once
+        std::vector<int32_t> lv;
+        for (int64_t e = b; e < b + d; ++e) lv.push_back(edge_exec_level[e]);
+        std::sort(lv.begin(), lv.end());
+        for (int32_t L : lv) {
+            if (L == prev) continue;
+            prev = L;
+            fac_by_level[L * FB_COUNT + bucket].push_back(a);
+            // bytes of a factor task: offsets, type, parameters, list entry; per edge: variable id,
+            // belief, old message, (level tag unless flooding), NOISY_OR activation
+            double per_edge = 4.0 + sizeof(Belief) + msg_bytes + (flooding ? 0 : 4) +
+                              (g.fac_type[a] == FASTLBP_NOISY_OR ? param_bytes : 0);
+            bytes_per_iter += 4 + 8 + 1 + param_bytes + per_edge * double(d);
+        }
+    }
+    // variables whose incoming messages a level writes: their beliefs are refreshed after it
+    for (int64_t e = 0; e < g.E; ++e) {
+        int32_t L = edge_exec_level[e];
+        if (L < 0) continue;
+        ++updates_per_iter;
+        bytes_per_iter += msg_bytes;  // written message
+        int32_t v = g.edge_var[e];
+        int vb = g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE;
+        var_by_level[L * VB_COUNT + vb].push_back(v);
+    }
+    for (auto &lst : var_by_level) {
+        std::sort(lst.begin(), lst.end());
+        lst.erase(std::unique(lst.begin(), lst.end()), lst.end());
+        // list entry, offsets, phi, belief write; per edge: edge id and message
+        for (int32_t v : lst) bytes_per_iter += 4 + 8 + 2 * sizeof(Belief) + double(g.var_deg[v]) * (4 + msg_bytes);
+    }
+    for (int b = 0; b < FB_COUNT; ++b) {
+        fac_list[b].clear();
+        fac_lvl_off[b].assign(1, 0);
+        for (int32_t L = 0; L < exec_levels; ++L) {
+            auto &src = fac_by_level[L * FB_COUNT + b];
+            // group factors of one type together so a wavefront mostly follows one code path
+            std::stable_sort(src.begin(), src.end(),
+                             [&](int32_t x, int32_t y) { return g.fac_type[x] < g.fac_type[y]; });
+            fac_list[b].insert(fac_list[b].end(), src.begin(), src.end());
+            fac_lvl_off[b].push_back(int32_t(fac_list[b].size()));
+        }
+    }
+    for (int b = 0; b < VB_COUNT; ++b) {
+        var_list[b].clear();
+        var_lvl_off[b].assign(1, 0);
+        for (int32_t L = 0; L < exec_levels; ++L) {
+            auto &src = var_by_level[L * VB_COUNT + b];
+            var_list[b].insert(var_list[b].end(), src.begin(), src.end());
+            var_lvl_off[b].push_back(int32_t(var_list[b].size()));
+        }
+        init_var[b].clear();
+    }
+    for (int32_t v = 0; v < g.V; ++v) init_var[g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE].push_back(v);
+}
+
+}  // namespace fastlbp
+
+extern "C" int fastlbp_graph_validate(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                                      const int32_t *edge_vars, const uint8_t *factor_types,
+                                      const double *factor_params, const double *edge_params) {
+    fastlbp::clear_error();
+    return fastlbp::validate_graph(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params,
+                                   edge_params);
+}
+
+extern "C" int fastlbp_analyze_levels(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                                      const int32_t *edge_vars, const int32_t *edge_rank, int32_t *level_of_edge,
+                                      int32_t *num_levels_out) {
+    fastlbp::clear_error();
+    if (num_vars < 0 || num_factors < 0 || !factor_offsets || !level_of_edge) {
+        fastlbp::set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (factor_offsets[0] != 0) {
+        fastlbp::set_error("factor_offsets[0] must be 0");
+        return FASTLBP_E_BAD_GRAPH;
+    }
+    for (int32_t a = 0; a < num_factors; ++a)
+        if (factor_offsets[a + 1] < factor_offsets[a]) {
+            fastlbp::set_error("factor_offsets must be non-decreasing");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    int64_t E = factor_offsets[num_factors];
+    for (int64_t e = 0; e < E; ++e)
+        if (edge_vars[e] < 0 || edge_vars[e] >= num_vars) {
+            fastlbp::set_error("variable id out of range");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    std::vector<int32_t> level;
+    int32_t n = fastlbp::analyze_levels(num_vars, num_factors, factor_offsets, edge_vars, edge_rank, level);
+    if (E) std::memcpy(level_of_edge, level.data(), sizeof(int32_t) * E);
+    if (num_levels_out) *num_levels_out = n;
+    return FASTLBP_OK;
+}

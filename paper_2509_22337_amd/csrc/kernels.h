@@ -1,0 +1,526 @@
+// Device code for the two phases of one level (Section 4.3.1): the factor phase computes the
+// factor-to-variable messages of the level's active edges (Eq.(2) through the local structure of
+// each factor type, Section 3.3), the variable phase refreshes the beliefs that Eq.(1) reads.
+//
+// Factor algebra. Every non-NOT type is an "any input fires" structure: input j carries weights
+// (h_j(x), a_j(x)) for not firing / firing given its value x, and the factor depends on its inputs
+// only through s = [some input fired]:
+//     OR        h = (1, 0), a = (0, 1)          f(x, y) = [y = s]
+//     AND       h = (0, 1), a = (1, 0)          f(x, y) = [y = !s]
+//     IMPLIES   h = (0, 1), a = (1, 0)          f = 1 if s; p if !s and y; 1-p if !s and !y
+//     NOISY_OR  h = (1, 1-p), a = (0, p)        f = P(y | s): cause-level OR, leak = extra cause
+// With normalised input messages m_j, each input contributes a leaf (H_j, F_j) = (sum_x m_j h_j,
+// sum_x m_j a_j) with H_j + F_j = 1. Segments combine associatively as
+//     (H_L, F_L) * (H_R, F_R) = (H_L H_R, F_L + H_L F_R),
+// i.e. "no cause fired in either" and "the first firing cause lies left, or none left and one
+// right". All terms are non-negative, so the same scan runs in the log domain without subtraction.
+// The message to the head needs the total (H, F); the message to input i needs the product of all
+// other leaves, prefix_i * suffix_i, which a forward and a backward scan give in O(degree).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.h"
+
+namespace fastlbp {
+
+enum { T_PRIOR = 0, T_AND = 1, T_OR = 2, T_NOT = 3, T_IMPLIES = 4, T_NOISY_OR = 5 };
+
+// ------------------------------------------------------------------------------------------------
+// Precision policies. S: stored message type (LLR in bits). V: value of the factor algebra.
+// ------------------------------------------------------------------------------------------------
+
+// float32, log2 domain: V holds log2 of a non-negative real.
+struct PolLog32 {
+    using S = float;
+    using V = float;
+    static __device__ __forceinline__ V zero() { return -__builtin_huge_valf(); }
+    static __device__ __forceinline__ V one() { return 0.0f; }
+    static __device__ __forceinline__ V mul(V a, V b) { return a + b; }
+    // log2(2^a + 2^b) without subtraction of large values
+    static __device__ __forceinline__ V add(V a, V b) {
+        V m = fmaxf(a, b), n = fminf(a, b);
+        if (m == -__builtin_huge_valf()) return m;
+        return m + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(n - m));
+    }
+    // normalised pair (log2 mu(0), log2 mu(1)) from an LLR l (bits); exact at l = +-inf
+    static __device__ __forceinline__ void leaf(S l, V &m0, V &m1) {
+        float t = __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-fabsf(l)));
+        m0 = -(fmaxf(l, 0.0f) + t);
+        m1 = -(fmaxf(-l, 0.0f) + t);
+    }
+    static __device__ __forceinline__ S llr(V v0, V v1, bool &contra) {
+        contra = (v0 == -__builtin_huge_valf()) && (v1 == -__builtin_huge_valf());
+        return contra ? 0.0f : v1 - v0;
+    }
+    static __device__ __forceinline__ S from_double(double x) { return (float)x; }
+};
+
+// float64, linear domain.
+struct PolLin64 {
+    using S = double;
+    using V = double;
+    static __device__ __forceinline__ V zero() { return 0.0; }
+    static __device__ __forceinline__ V one() { return 1.0; }
+    static __device__ __forceinline__ V mul(V a, V b) { return a * b; }
+    static __device__ __forceinline__ V add(V a, V b) { return a + b; }
+    static __device__ __forceinline__ void leaf(S l, V &m0, V &m1) {
+        double e = exp2(-fabs(l));
+        double r = 1.0 / (1.0 + e);
+        if (l >= 0.0) {
+            m1 = r;
+            m0 = e * r;
+        } else {
+            m0 = r;
+            m1 = e * r;
+        }
+    }
+    static __device__ __forceinline__ S llr(V v0, V v1, bool &contra) {
+        contra = (v0 == 0.0) && (v1 == 0.0);
+        return contra ? 0.0 : log2(v1) - log2(v0);
+    }
+    static __device__ __forceinline__ S from_double(double x) { return x; }
+};
+
+// P(x = 1) of an LLR in bits, in float64 (used for the residual).
+__device__ __forceinline__ double prob1(double l) { return 1.0 / (1.0 + exp2(-l)); }
+
+// Variable-to-factor message of Eq.(1) from the variable's belief minus the factor's own incoming
+// message. `null` marks the product of two exact zeros (0, 0).
+template <class P>
+__device__ __forceinline__ typename P::S v2f(const Belief &B, typename P::S own, bool &null) {
+    using S = typename P::S;
+    const S inf = (S)__builtin_huge_val();
+    int np = B.npos - (own == inf ? 1 : 0);
+    int nn = B.nneg - (own == -inf ? 1 : 0);
+    null = (np > 0) && (nn > 0);
+    if (null) return (S)0;
+    if (np > 0) return inf;
+    if (nn > 0) return -inf;
+    double f = B.fin - ((own == inf || own == -inf) ? 0.0 : (double)own);
+    return P::from_double(f);
+}
+
+template <class V>
+struct HF {
+    V h, f;
+};
+
+template <class P>
+__device__ __forceinline__ HF<typename P::V> combine(HF<typename P::V> L, HF<typename P::V> R) {
+    return {P::mul(L.h, R.h), P::add(L.f, P::mul(L.h, R.f))};
+}
+
+template <class P>
+__device__ __forceinline__ HF<typename P::V> identity() {
+    return {P::one(), P::zero()};
+}
+
+// Leaf of input j from its normalised message (m0, m1).
+template <class P>
+__device__ __forceinline__ HF<typename P::V> make_leaf(int type, typename P::V m0, typename P::V m1,
+                                                       const Pair<typename P::V> &ep) {
+    if (type == T_OR) return {m0, m1};
+    if (type == T_NOISY_OR) return {P::add(m0, P::mul(m1, ep.b)), P::mul(m1, ep.a)};
+    return {m1, m0};  // AND, IMPLIES: an input fires when it is 0
+}
+
+// Unnormalised message to the head from the total (H, F) of all inputs (leak included).
+template <class P>
+__device__ __forceinline__ void head_msg(int type, HF<typename P::V> t, const Pair<typename P::V> &fp,
+                                         typename P::V &o0, typename P::V &o1) {
+    if (type == T_OR || type == T_NOISY_OR) {
+        o0 = t.h;
+        o1 = t.f;
+    } else if (type == T_AND) {
+        o0 = t.f;
+        o1 = t.h;
+    } else {  // IMPLIES: fp = (p, 1-p)
+        o0 = P::add(P::mul(fp.b, t.h), t.f);
+        o1 = P::add(P::mul(fp.a, t.h), t.f);
+    }
+}
+
+// Unnormalised message to input i from the product x of the other inputs' leaves (leak included),
+// the head's normalised message (my0, my1) and the input's own parameters.
+template <class P>
+__device__ __forceinline__ void input_msg(int type, HF<typename P::V> x, typename P::V my0, typename P::V my1,
+                                          const Pair<typename P::V> &fp, const Pair<typename P::V> &ep,
+                                          typename P::V &o0, typename P::V &o1) {
+    using V = typename P::V;
+    if (type == T_OR || type == T_NOISY_OR) {
+        V base = P::add(P::mul(my0, x.h), P::mul(my1, x.f));  // input i does not fire
+        o0 = base;
+        o1 = (type == T_OR) ? my1 : P::add(P::mul(ep.b, base), P::mul(ep.a, my1));
+    } else if (type == T_AND) {
+        o0 = my0;
+        o1 = P::add(P::mul(my1, x.h), P::mul(my0, x.f));
+    } else {  // IMPLIES
+        V s = P::add(my0, my1);
+        V wy = P::add(P::mul(my0, fp.b), P::mul(my1, fp.a));
+        o0 = s;
+        o1 = P::add(P::mul(wy, x.h), P::mul(s, x.f));
+    }
+}
+
+// Per-thread accumulators of the residual and the contradiction count.
+struct Acc {
+    double r;
+    unsigned int contra;
+};
+
+// Writes the new message of edge e (damping, residual, contradiction handling).
+template <class P, bool DAMP>
+__device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename P::V> &g, int32_t e,
+                                          typename P::S old, typename P::V o0, typename P::V o1, bool force_contra,
+                                          Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    bool contra;
+    S l = P::llr(o0, o1, contra);
+    if (force_contra) {
+        contra = true;
+        l = (S)0;
+    }
+    if (contra) acc.contra++;
+    if (DAMP) {
+        V a0, a1, b0, b1;
+        P::leaf(old, a0, a1);
+        P::leaf(l, b0, b1);
+        bool c2;
+        l = P::llr(P::add(P::mul(g.damp_old, a0), P::mul(g.damp_new, b0)),
+                   P::add(P::mul(g.damp_old, a1), P::mul(g.damp_new, b1)), c2);
+    }
+    double d = fabs(prob1((double)l) - prob1((double)old));
+    acc.r = fmax(acc.r, d);
+    g.msg[e] = l;
+}
+
+template <bool ALL_ACTIVE>
+__device__ __forceinline__ bool is_active(const int32_t *edge_level, int32_t e, int level) {
+    return ALL_ACTIVE || edge_level[e] == level;
+}
+
+// NOT factor: the message to y is the input's message reversed, and vice versa.
+template <class P, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_not(const DevGraph<typename P::S, typename P::V> &g, int32_t b, int level, Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    S lo[2], vf[2];
+    bool nl[2];
+    for (int k = 0; k < 2; ++k) {
+        lo[k] = g.msg[b + k];
+        vf[k] = v2f<P>(g.bel[g.edge_var[b + k]], lo[k], nl[k]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!is_active<ALL_ACTIVE>(g.edge_level, b + k, level)) continue;
+        V m0, m1;
+        P::leaf(-vf[1 - k], m0, m1);
+        store_msg<P, DAMP>(g, b + k, lo[k], m0, m1, nl[1 - k], acc);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// One factor processed by a team of TEAM lanes (TEAM = 1: a single thread; 64: a wavefront;
+// > 64: a whole workgroup using `lds`). Lane `lane` owns a contiguous chunk of at most CMAX inputs.
+// ------------------------------------------------------------------------------------------------
+
+template <class V>
+struct TeamLds {
+    HF<V> wave_tot[16];
+    HF<V> wave_pre[16];
+    HF<V> wave_suf[16];
+    int wave_null[16];
+    int null_total;
+    HF<V> total;
+};
+
+template <class P, int TEAM>
+struct TeamScan;
+
+// Exclusive prefix and suffix of per-lane aggregates across the team; also the team-wide total and
+// the number of null inputs. `init` is the leftmost element (the NOISY_OR leak, else identity).
+template <class P>
+struct TeamScan<P, 1> {
+    using V = typename P::V;
+    static __device__ __forceinline__ void run(HF<V> agg, int nnull, HF<V> init, HF<V> &pre, HF<V> &suf, HF<V> &tot, int &ntot,
+                               TeamLds<V> *) {
+        pre = init;
+        suf = identity<P>();
+        tot = combine<P>(init, agg);
+        ntot = nnull;
+    }
+};
+
+template <class P>
+__device__ __forceinline__ void wave_scans(HF<typename P::V> x, int lane, HF<typename P::V> &incl_pre,
+                                           HF<typename P::V> &incl_suf) {
+    using V = typename P::V;
+    HF<V> p = x, s = x;
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+        V ph = __shfl_up(p.h, k, 64), pf = __shfl_up(p.f, k, 64);
+        if (lane >= k) p = combine<P>({ph, pf}, p);
+        V sh = __shfl_down(s.h, k, 64), sf = __shfl_down(s.f, k, 64);
+        if (lane + k < 64) s = combine<P>(s, {sh, sf});
+    }
+    incl_pre = p;
+    incl_suf = s;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) x += __shfl_xor(x, k, 64);
+    return x;
+}
+
+template <class P>
+struct TeamScan<P, 64> {
+    using V = typename P::V;
+    static __device__ __forceinline__ void run(HF<V> agg, int nnull, HF<V> init, HF<V> &pre, HF<V> &suf, HF<V> &tot, int &ntot,
+                               TeamLds<V> *) {
+        int lane = threadIdx.x & 63;
+        HF<V> ip, is;
+        wave_scans<P>(agg, lane, ip, is);
+        HF<V> ep = {__shfl_up(ip.h, 1, 64), __shfl_up(ip.f, 1, 64)};
+        HF<V> es = {__shfl_down(is.h, 1, 64), __shfl_down(is.f, 1, 64)};
+        pre = (lane == 0) ? init : combine<P>(init, ep);
+        suf = (lane == 63) ? identity<P>() : es;
+        HF<V> all = {__shfl(ip.h, 63, 64), __shfl(ip.f, 63, 64)};
+        tot = combine<P>(init, all);
+        ntot = wave_sum(nnull);
+    }
+};
+
+template <class P, int TEAM>
+struct TeamScan {
+    using V = typename P::V;
+    static_assert(TEAM % 64 == 0 && TEAM / 64 <= 16, "team is up to 16 wavefronts");
+    static __device__ __forceinline__ void run(HF<V> agg, int nnull, HF<V> init, HF<V> &pre, HF<V> &suf, HF<V> &tot, int &ntot,
+                               TeamLds<V> *lds) {
+        constexpr int NW = TEAM / 64;
+        int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        HF<V> ip, is;
+        wave_scans<P>(agg, lane, ip, is);
+        HF<V> ep = {__shfl_up(ip.h, 1, 64), __shfl_up(ip.f, 1, 64)};
+        HF<V> es = {__shfl_down(is.h, 1, 64), __shfl_down(is.f, 1, 64)};
+        int wn = wave_sum(nnull);
+        if (lane == 63) lds->wave_tot[w] = ip;
+        if (lane == 0) lds->wave_null[w] = wn;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            HF<V> run = init;
+            int nt = 0;
+            for (int i = 0; i < NW; ++i) {
+                lds->wave_pre[i] = run;
+                run = combine<P>(run, lds->wave_tot[i]);
+                nt += lds->wave_null[i];
+            }
+            lds->total = run;
+            lds->null_total = nt;
+            HF<V> r = identity<P>();
+            for (int i = NW - 1; i >= 0; --i) {
+                lds->wave_suf[i] = r;
+                r = combine<P>(lds->wave_tot[i], r);
+            }
+        }
+        __syncthreads();
+        HF<V> wp = lds->wave_pre[w], ws = lds->wave_suf[w];
+        pre = (lane == 0) ? wp : combine<P>(wp, ep);
+        suf = (lane == 63) ? ws : combine<P>(es, ws);
+        tot = lds->total;
+        ntot = lds->null_total;
+        __syncthreads();  // lds is reused by the next factor
+    }
+};
+
+// Reads input i of factor (b, d): its old message, its v->f message and its leaf.
+template <class P>
+__device__ __forceinline__ HF<typename P::V> load_leaf(const DevGraph<typename P::S, typename P::V> &g, int type,
+                                                       int32_t e, typename P::S &old, bool &null) {
+    using V = typename P::V;
+    old = g.msg[e];
+    typename P::S vf = v2f<P>(g.bel[g.edge_var[e]], old, null);
+    if (null) return identity<P>();
+    V m0, m1;
+    P::leaf(vf, m0, m1);
+    Pair<V> ep = {P::zero(), P::one()};
+    if (type == T_NOISY_OR) ep = g.epar[e];
+    return make_leaf<P>(type, m0, m1, ep);
+}
+
+// Writes the messages of the head and of every active input of factor a. TEAM = 1 keeps the
+// leaves of its (at most CMAX) inputs in registers. A team splits each lane's chunk into sub-chunks
+// of 4 and re-reads leaves (cache hits) instead of holding them, so that a 1024-lane workgroup stays
+// within its 128-register budget in float64 without spilling.
+template <class P, int TEAM, int CMAX, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int lane, int level,
+                            Acc &acc, TeamLds<typename P::V> *lds) {
+    using S = typename P::S;
+    using V = typename P::V;
+    constexpr bool KEEP = (TEAM == 1);
+    constexpr int SB = KEEP ? CMAX : 4;         // sub-chunk length
+    constexpr int NS = (CMAX + SB - 1) / SB;    // sub-chunks per lane
+    const int32_t b = g.fac_off[a];
+    const int32_t d = g.fac_off[a + 1] - b;
+    const int type = g.fac_type[a];
+    if (type == T_NOT) {
+        if (lane == 0) factor_not<P, ALL_ACTIVE, DAMP>(g, b, level, acc);
+        return;
+    }
+    const int32_t n = d - 1;
+    const Pair<V> fp = g.fpar[a];
+    // head (last edge): its v->f message weights the messages to the inputs
+    const int32_t eh = b + n;
+    S lh_old = g.msg[eh];
+    bool null_h;
+    S vfh = v2f<P>(g.bel[g.edge_var[eh]], lh_old, null_h);
+    V my0 = P::zero(), my1 = P::zero();
+    if (!null_h) P::leaf(vfh, my0, my1);
+    // chunk of inputs owned by this lane
+    const int32_t c = (n + TEAM - 1) / TEAM;
+    const int32_t i0 = min(n, lane * c), i1 = min(n, i0 + c);
+    HF<V> lf[KEEP ? CMAX : 1];
+    S lo[KEEP ? CMAX : 1];
+    bool ln[KEEP ? CMAX : 1];
+    HF<V> sub[NS];  // aggregate of each sub-chunk, later the prefix before it
+    int nnull = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sub[s] = identity<P>();
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int k = s * SB + j;
+            if (k < CMAX && i0 + k < i1) {
+                S o;
+                bool nl;
+                HF<V> x = load_leaf<P>(g, type, b + i0 + k, o, nl);
+                if (KEEP) {
+                    lf[KEEP ? k : 0] = x;
+                    lo[KEEP ? k : 0] = o;
+                    ln[KEEP ? k : 0] = nl;
+                }
+                nnull += nl ? 1 : 0;
+                sub[s] = combine<P>(sub[s], x);
+            }
+        }
+    }
+    HF<V> agg = sub[0];
+#pragma unroll
+    for (int s = 1; s < NS; ++s) agg = combine<P>(agg, sub[s]);
+    HF<V> init = identity<P>();
+    if (type == T_NOISY_OR) init = {fp.b, fp.a};  // the leak: fires with probability leak
+    HF<V> pre, suf, tot;
+    int ntot;
+    TeamScan<P, TEAM>::run(agg, nnull, init, pre, suf, tot, ntot, lds);
+    if (lane == 0 && is_active<ALL_ACTIVE>(g.edge_level, eh, level)) {
+        V o0, o1;
+        head_msg<P>(type, tot, fp, o0, o1);
+        store_msg<P, DAMP>(g, eh, lh_old, o0, o1, ntot > 0, acc);
+    }
+    // prefix before each sub-chunk
+    {
+        HF<V> run = pre;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            HF<V> t = sub[s];
+            sub[s] = run;
+            run = combine<P>(run, t);
+        }
+    }
+    // sub-chunks from last to first: suffix inside the sub-chunk, then the exclusive products
+    HF<V> rsuf = suf;
+#pragma unroll
+    for (int s = NS - 1; s >= 0; --s) {
+        HF<V> sx[SB];
+        HF<V> run = rsuf;
+#pragma unroll
+        for (int j = SB - 1; j >= 0; --j) {
+            const int k = s * SB + j;
+            if (k < CMAX && i0 + k < i1) {
+                sx[j] = run;
+                HF<V> x;
+                if (KEEP) {
+                    x = lf[KEEP ? k : 0];
+                } else {
+                    S o;
+                    bool nl;
+                    x = load_leaf<P>(g, type, b + i0 + k, o, nl);
+                }
+                run = combine<P>(x, run);
+            }
+        }
+        rsuf = run;
+        run = sub[s];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int k = s * SB + j;
+            if (k < CMAX && i0 + k < i1) {
+                const int32_t e = b + i0 + k;
+                S o;
+                bool nl;
+                HF<V> x;
+                if (KEEP) {
+                    x = lf[KEEP ? k : 0];
+                    o = lo[KEEP ? k : 0];
+                    nl = ln[KEEP ? k : 0];
+                } else {
+                    x = load_leaf<P>(g, type, e, o, nl);
+                }
+                if (is_active<ALL_ACTIVE>(g.edge_level, e, level)) {
+                    HF<V> xo = combine<P>(run, sx[j]);
+                    Pair<V> ep = {P::zero(), P::one()};
+                    if (type == T_NOISY_OR) ep = g.epar[e];
+                    V o0, o1;
+                    input_msg<P>(type, xo, my0, my1, fp, ep, o0, o1);
+                    int others_null = ntot - (nl ? 1 : 0) + (null_h ? 1 : 0);
+                    store_msg<P, DAMP>(g, e, o, o0, o1, others_null > 0, acc);
+                }
+                run = combine<P>(run, x);
+            }
+        }
+    }
+}
+
+// Variable phase: B_v = phi_v + sum of the v's incoming non-PRIOR messages (float64, with counts).
+template <class P>
+__device__ __forceinline__ void belief_add(Belief &B, typename P::S l) {
+    using S = typename P::S;
+    const S inf = (S)__builtin_huge_val();
+    if (l == inf)
+        B.npos++;
+    else if (l == -inf)
+        B.nneg++;
+    else
+        B.fin += (double)l;
+}
+
+template <class P>
+__device__ __forceinline__ void var_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t v) {
+    Belief B = g.phi[v];
+    for (int32_t q = g.var_off[v]; q < g.var_off[v + 1]; ++q) belief_add<P>(B, g.msg[g.var_edge[q]]);
+    g.bel[v] = B;
+}
+
+// One wavefront per variable (high degree); fixed-shape reduction, so the result is deterministic.
+template <class P>
+__device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename P::V> &g, int32_t v, int lane) {
+    Belief B = {0.0, 0, 0};
+    for (int32_t q = g.var_off[v] + lane; q < g.var_off[v + 1]; q += 64) belief_add<P>(B, g.msg[g.var_edge[q]]);
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) {
+        B.fin += __shfl_xor(B.fin, k, 64);
+        B.npos += __shfl_xor(B.npos, k, 64);
+        B.nneg += __shfl_xor(B.nneg, k, 64);
+    }
+    if (lane == 0) {
+        Belief p = g.phi[v];
+        p.fin += B.fin;
+        p.npos += B.npos;
+        p.nneg += B.nneg;
+        g.bel[v] = p;
+    }
+}
+
+}  // namespace fastlbp

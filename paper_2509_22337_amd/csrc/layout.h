@@ -1,0 +1,85 @@
+// Device data layout shared by the host planner and the HIP kernels.
+//
+// Edges keep the caller's factor-major numbering. Messages f->v live in one array indexed by
+// edge id (stored as log-likelihood ratios in log2 units, "bits": l = log2 mu(1) - log2 mu(0)),
+// so the factor phase reads and writes each factor's messages contiguously. Every variable keeps a
+// belief record B_v = phi_v + sum over its non-PRIOR edges of l, accumulated in float64 with
+// separate counts of +inf and -inf terms; the variable-to-factor message of Eq.(1) is then
+// B_v minus the factor's own incoming message, which the factor phase forms on the fly. PRIOR
+// factors are folded into phi_v together with evidence, so they never occupy message slots on the
+// device.
+#pragma once
+#include <cstdint>
+
+namespace fastlbp {
+
+// Finite part plus counts of infinite terms of a sum of LLRs. A sum with both +inf and -inf
+// terms is the product of two exactly-zero entries: the "null" message (0, 0).
+struct Belief {
+    double fin;
+    int32_t npos;
+    int32_t nneg;
+};
+
+template <typename V>
+struct Pair {
+    V a;  // parameter p (NOISY_OR activation / leak, IMPLIES weight) in the precision's value domain
+    V b;  // 1 - p in the same domain
+};
+
+// Per-run state in device memory. Every kernel of a captured iteration returns immediately once
+// `done` is set, so replaying more iterations than needed is harmless.
+struct RunState {
+    unsigned long long rbits;   // residual of the current iteration: max |dP(x=1)|, as double bits
+    unsigned long long contra;  // messages replaced by uniform during the run
+    int32_t iter;               // iterations completed
+    int32_t done;               // 1 once converged or max_iters reached
+    double last_r;              // residual of the last completed iteration
+    int32_t max_iters;
+    int32_t converged;
+    double tol;
+};
+
+// Degree buckets. Factor degree d = inputs + head.
+constexpr int kThreadMaxDeg = 8;     // one thread per factor
+constexpr int kWaveMaxDeg = 1025;    // one wavefront per factor: 64 lanes x 16 inputs + head
+constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 1024 x 16 + head
+constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
+
+enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_COUNT = 3 };
+enum { VB_THREAD = 0, VB_WAVE = 1, VB_COUNT = 2 };
+
+template <typename S, typename V>
+struct DevGraph {
+    int32_t num_vars;
+    int32_t num_edges;
+    const int32_t *fac_off;    // [F+1]
+    const int32_t *edge_var;   // [E]
+    const uint8_t *fac_type;   // [F]
+    const Pair<V> *fpar;       // [F]
+    const Pair<V> *epar;       // [E]
+    const int32_t *var_off;    // [V+1] over non-PRIOR edges
+    const int32_t *var_edge;   // [E_np] edge ids, variable-major
+    const Belief *phi;         // [V] priors + evidence
+    Belief *bel;               // [V]
+    S *msg;                    // [E]
+    const int32_t *edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
+    V damp_old;                // lambda in the value domain
+    V damp_new;                // 1 - lambda in the value domain
+};
+
+// Work lists of one schedule, concatenated over the executed levels. Level L owns
+// fac_list[b][fac_lvl_off[b][L] .. fac_lvl_off[b][L+1]) for every factor bucket b, and the same for
+// variables. init_var lists every variable (all levels' beliefs are rebuilt from it at run start).
+struct DevPlan {
+    int32_t num_levels;
+    int32_t all_active;  // 1: every listed factor writes all of its edges (flooding)
+    const int32_t *fac_list[FB_COUNT];
+    const int32_t *fac_lvl_off[FB_COUNT];  // [num_levels+1]
+    const int32_t *var_list[VB_COUNT];
+    const int32_t *var_lvl_off[VB_COUNT];  // [num_levels+1]
+    const int32_t *init_var[VB_COUNT];
+    int32_t init_var_count[VB_COUNT];
+};
+
+}  // namespace fastlbp

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on the same seeded
+inputs. Tolerances: marginals within 1e-9 absolute in FP64 and 1e-4 absolute in FP32; level
+indexing bit-exact; iteration counts equal in FP64."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_22337_amd as F
+from oracle import reference as R
+from paper_2509_22337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _gpu_run(w, precision="fp64", executor="auto", ranks="auto", max_iters=None, tol=None, damping=None,
+             use_graph=True, msg1=None):
+    g = F.Graph(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, precision=precision,
+                executor=executor, use_graph=use_graph)
+    rk = w.edge_rank if isinstance(ranks, str) else ranks
+    if rk is not None:
+        g.schedule_set(F.SCHED_RANKED, rk)
+    if w.evidence is not None:
+        g.evidence_array(w.evidence)
+    if msg1 is not None:
+        g.messages_set(msg1)
+    st = g.run(w.max_iters if max_iters is None else max_iters, w.tol if tol is None else tol,
+               w.damping if damping is None else damping)
+    m = g.marginals()
+    msgs = g.messages_get()
+    lv = g.schedule_levels()
+    g.close()
+    return m, msgs, st, lv
+
+
+def _sensitive(w, ranks, max_iters, tol, damping):
+    """Chaos guard: does a 1e-15 perturbation of the start state move the oracle's marginals by
+    more than 1e-10? Then end-to-end parity is replaced by one-step parity for this instance."""
+    a, _, _ = oracle.bp(w, max_iters, tol, damping, ranks=ranks)
+    rng = np.random.default_rng(0)
+    m1 = 0.5 + 1e-15 * rng.standard_normal(w.num_edges)
+    b, _, _ = oracle.bp(w, max_iters, tol, damping, ranks=ranks, msg1=m1)
+    return np.abs(a - b).max() > 1e-10
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trees_exact(executor, precision):
+    for seed in range(12):
+        w = W.random_tree(seed, num_vars=14)
+        exact, Z = R.exact_marginals(w)
+        if Z <= 0:
+            continue
+        it = 2 * w.num_vars + 4
+        _say("tree", seed, executor, precision)
+        m, _, st, _ = _gpu_run(w, precision, executor, ranks=None, max_iters=it, tol=0.0, damping=0.0)
+        om, _, ost = oracle.bp(w, it, 0.0, 0.0, ranks=None)
+        assert np.abs(m - om).max() <= TOL[precision], seed
+        assert np.abs(m - exact).max() <= TOL[precision], seed
+        assert st["iterations"] == ost["iterations"] == it
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+def test_loopy_flooding_fp64(executor):
+    for seed in range(10):
+        w = W.random_loopy(seed)
+        args = (40, 1e-12, 0.3)
+        if _sensitive(w, None, *args):
+            continue
+        _say("loopy", seed, executor)
+        m, msgs, st, _ = _gpu_run(w, "fp64", executor, ranks=None, max_iters=40, tol=1e-12, damping=0.3)
+        om, omsg, ost = oracle.bp(w, *args, ranks=None)
+        assert np.abs(m - om).max() <= 1e-9, seed
+        assert np.abs(msgs - omsg).max() <= 1e-9, seed
+        assert st["iterations"] == ost["iterations"], seed
+        assert st["contradictions"] == ost["contradictions"]
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+@pytest.mark.parametrize("kind", ["ties", "total"])
+def test_ranked_schedules_fp64(executor, kind):
+    for seed in range(8):
+        w = W.random_loopy(100 + seed, num_vars=30, num_factors=40)
+        rng = np.random.default_rng(seed)
+        ranks = (rng.integers(0, 5, w.num_edges) if kind == "ties" else rng.permutation(w.num_edges)).astype(np.int32)
+        args = (25, 0.0, 0.2)
+        if _sensitive(w, ranks, *args):
+            continue
+        _say("ranked", kind, seed, executor)
+        m, msgs, st, lv = _gpu_run(w, "fp64", executor, ranks=ranks, max_iters=25, tol=0.0, damping=0.2)
+        om, omsg, ost = oracle.bp(w, *args, ranks=ranks)
+        assert np.abs(m - om).max() <= 1e-9
+        assert np.abs(msgs - omsg).max() <= 1e-9
+        assert np.array_equal(lv, R.alg2_class_atomic(w, ranks).astype(np.int32))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+def test_datalog_c1(precision, executor):
+    w = W.datalog(0)
+    _say("C1", precision, executor)
+    m, msgs, st, _ = _gpu_run(w, precision, executor)
+    om, omsg, ost = oracle.bp(w)
+    err = np.abs(m - om).max()
+    _say("  C1 err", err, "iters", st["iterations"])
+    assert err <= TOL[precision]
+    assert st["iterations"] == ost["iterations"] == 50
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_smartfl_small_ranked(precision):
+    w = W.smartfl(1, levels=40, width=100, max_iters=60)
+    _say("C2-small", precision)
+    m, _, st, lv = _gpu_run(w, precision)
+    om, _, ost = oracle.bp(w)
+    err = np.abs(m - om).max()
+    _say("  err", err, "iters", st["iterations"], ost["iterations"], "contra", st["contradictions"])
+    assert err <= TOL[precision]
+    if precision == "fp64":
+        assert st["iterations"] == ost["iterations"]
+        assert st["contradictions"] == ost["contradictions"]
+    assert np.array_equal(lv, R.alg2_class_atomic(w, w.edge_rank).astype(np.int32))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_smartfl_full_size(precision):
+    # the full 200k-variable configuration, in the executor the benchmark times
+    w = W.smartfl(0)
+    _say("C2-full", precision)
+    m, _, st, lv = _gpu_run(w, precision)
+    om, _, ost = oracle.bp(w)
+    err = np.abs(m - om).max()
+    _say("  err", err, "iters", st["iterations"], ost["iterations"], "executor", st["executor"], "ms", st["device_ms"])
+    assert err <= TOL[precision]
+    if precision == "fp64":
+        assert st["iterations"] == ost["iterations"]
+    lib_lv, _ = F.analyze_levels(w.num_vars, w.fac_off, w.edge_var, w.edge_rank)
+    assert np.array_equal(lv, lib_lv)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_fanin_buckets(precision):
+    # noisy-or fan-in up to several thousand: thread, wavefront and workgroup buckets all used
+    w = W.bingo(3, num_tuples=20_000, num_rules=40_000, max_iters=4)
+    deg = np.diff(w.fac_off)
+    assert deg.max() > 1025 and ((deg > 8) & (deg <= 1025)).any()
+    _say("bingo-small", precision, deg.max())
+    for executor in ("levels", "persistent"):
+        m, msgs, st, _ = _gpu_run(w, precision, executor, max_iters=4, tol=0.0, damping=0.0)
+        om, omsg, _ = oracle.bp(w, 4, 0.0, 0.0)
+        err = np.abs(m - om).max()
+        _say("  ", executor, "err", err)
+        assert err <= TOL[precision]
+        assert np.abs(msgs - omsg).max() <= (1e-9 if precision == "fp64" else 2e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_one_step_parity(precision):
+    # same start state (including exact 0/1 messages), one iteration of a ranked schedule
+    w = W.random_loopy(7, num_vars=60, num_factors=90, max_arity=9)
+    rng = np.random.default_rng(5)
+    p1 = rng.uniform(0, 1, w.num_edges)
+    p1[rng.random(w.num_edges) < 0.1] = 1.0
+    p1[rng.random(w.num_edges) < 0.1] = 0.0
+    pri = np.repeat(w.fac_type, np.diff(w.fac_off)) == W.PRIOR
+    p1[pri] = np.repeat(w.fac_param, np.diff(w.fac_off))[pri]
+    ranks = rng.integers(0, 3, w.num_edges).astype(np.int32)
+    for executor in ("levels", "persistent"):
+        _, msgs, st, _ = _gpu_run(w, precision, executor, ranks=ranks, max_iters=1, tol=0.0, damping=0.25, msg1=p1)
+        _, _, om1, ost = oracle.bp_pairs(w, 1 - p1, p1, 1, 0.0, 0.25, ranks=ranks)
+        tol = 1e-12 if precision == "fp64" else 1e-5
+        assert np.abs(msgs - om1).max() <= tol
+        assert st["contradictions"] == ost["contradictions"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_evidence_warm_start_matches_oracle(precision):
+    # the interactive loop: run, change the clamps, re-run from the resident messages. Each side
+    # warm-starts from its own state (P(x=1) in float64 cannot carry messages whose odds exceed
+    # 2^53, so a state read back through messages_get is not an exact restart point).
+    w = W.smartfl(2, levels=30, width=60, max_iters=40)
+    ev2 = W.smartfl_evidence(w, seed=9)
+    g = F.Graph.from_workload(w, precision=precision)
+    g.run(w.max_iters, w.tol, 0.0)
+    g.evidence_array(ev2)
+    st = g.run(w.max_iters, w.tol, 0.0)
+    m = g.marginals()
+    g.close()
+    _, om0, om1, _ = oracle.bp_pairs(w, np.full(w.num_edges, 0.5), np.full(w.num_edges, 0.5), w.max_iters,
+                                     w.tol, 0.0, ranks=w.edge_rank)
+    om, _, _, ost = oracle.bp_pairs(w, om0, om1, w.max_iters, w.tol, 0.0, ranks=w.edge_rank, evidence=ev2)
+    assert np.abs(m - om).max() <= TOL[precision]
+    if precision == "fp64":
+        assert st["iterations"] == ost["iterations"]
+
+
+def test_contradictions_counted_like_oracle():
+    # AND(x0, x1) -> y with y clamped to 1 and x0 clamped to 0: no world satisfies the evidence
+    b = W._Builder(4)
+    b.add(W.AND, [0, 1, 2])
+    b.add(W.OR, [1, 3, 2])
+    b.add(W.PRIOR, [1], 0.3)
+    w = b.build(evidence=np.array([0, -1, 1, -1], dtype=np.int8))
+    for precision in ("fp64", "fp32"):
+        for executor in ("levels", "persistent"):
+            m, msgs, st, _ = _gpu_run(w, precision, executor, ranks=None, max_iters=5, tol=0.0, damping=0.0)
+            om, omsg, ost = oracle.bp(w, 5, 0.0, 0.0, ranks=None)
+            assert st["contradictions"] == ost["contradictions"] > 0
+            assert np.abs(m - om).max() <= TOL[precision]
+
+
+def test_degenerate_graphs():
+    # no factors at all; only priors; a single NOT; evidence on an isolated variable
+    w = W.Workload(num_vars=3, fac_off=np.zeros(1, np.int64), edge_var=np.zeros(0, np.int32),
+                   fac_type=np.zeros(0, np.uint8), fac_param=np.zeros(0), edge_param=np.zeros(0),
+                   evidence=np.array([-1, 1, 0], np.int8), max_iters=3)
+    m, _, st, _ = _gpu_run(w, ranks=None)
+    assert m.tolist() == [0.5, 1.0, 0.0] and st["iterations"] == 3
+    b = W._Builder(2)
+    b.add(W.PRIOR, [0], 0.2)
+    b.add(W.PRIOR, [0], 0.7)
+    b.add(W.NOT, [0, 1])
+    w = b.build(evidence=np.full(2, -1, np.int8), max_iters=3)
+    m, _, _, _ = _gpu_run(w, ranks=None)
+    om, _, _ = oracle.bp(w, 3, 0.0, 0.0, ranks=None)
+    assert np.abs(m - om).max() <= 1e-12
+    # zero iterations leave messages uniform
+    m0, msgs, st, _ = _gpu_run(w, ranks=None, max_iters=0)
+    assert st["iterations"] == 0
+    assert np.all(msgs[w.fac_type.repeat(np.diff(w.fac_off)) != W.PRIOR] == 0.5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_executors_and_graph_replay_agree(precision):
+    w = W.smartfl(4, levels=25, width=80, max_iters=30)
+    a = _gpu_run(w, precision, "levels", use_graph=True)
+    b = _gpu_run(w, precision, "levels", use_graph=False)
+    c = _gpu_run(w, precision, "persistent")
+    assert np.array_equal(a[1], b[1])  # same kernels, same order: bit-identical
+    assert np.abs(a[0] - c[0]).max() <= (1e-12 if precision == "fp64" else 1e-5)
+    assert a[2]["iterations"] == b[2]["iterations"]
+
+
+def test_messages_roundtrip_and_reset():
+    w = W.datalog(1)
+    g = F.Graph.from_workload(w, precision="fp64")
+    g.run(10, 0.0, 0.5)
+    msgs = g.messages_get()
+    g.messages_reset()
+    assert np.all(g.messages_get()[np.repeat(w.fac_type, np.diff(w.fac_off)) != W.PRIOR] == 0.5)
+    g.messages_set(msgs)
+    assert np.abs(g.messages_get() - msgs).max() <= 1e-15
+    with pytest.raises(F.FastLBPError):
+        g.messages_set(np.full(w.num_edges, 2.0))
+    with pytest.raises(F.FastLBPError):
+        g.run(5, -1.0, 0.0)
+    with pytest.raises(F.FastLBPError):
+        g.run(5, 0.0, 1.0)
+    g.close()
