@@ -140,6 +140,13 @@ int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *f
 
 void fastlbp_graph_destroy(fastlbp_graph_t g);
 
+/* Creates a second handle on the same graph: it shares the device structure and the current
+ * schedule with `src` (no copy) and has its own messages (uniform), evidence (none) and stream.
+ * Used to run many queries of one graph side by side (fastlbp_run_batch). A later
+ * fastlbp_schedule_set on either handle gives that handle its own plan. The structure is freed
+ * with the last handle that uses it. Errors: E_INVALID_ARG, E_OOM, E_DEVICE. */
+int fastlbp_graph_clone(fastlbp_graph_t src, fastlbp_graph_t *out);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Update strategy and dependency analysis (Section 4.2, Definition 2, Algorithm 2)             */
 /* ------------------------------------------------------------------------------------------ */
@@ -185,6 +192,15 @@ int fastlbp_evidence_clear(fastlbp_graph_t g);
  * damping lambda in [0,1). stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
 int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
 
+/* Runs n handles side by side in one launch of the persistent executor (one workgroup per
+ * handle): each handle runs from its own message state and evidence, exactly as fastlbp_run with
+ * FASTLBP_EXEC_PERSISTENT would, with the same max_iters, tol and damping. The handles may belong
+ * to different graphs but must share one device and one precision, and none may appear twice.
+ * stats [n] may be NULL; device_ms is the time of the whole launch. Errors: E_INVALID_ARG,
+ * E_OOM, E_DEVICE. */
+int fastlbp_run_batch(int32_t n, fastlbp_graph_t *graphs, int32_t max_iters, double tol, double damping,
+                      fastlbp_run_stats *stats);
+
 /* Marginals P(X_v = 1) [V] of Eq.(3) from the current messages, evidence and priors (float64).
  * A variable whose incoming messages contradict (all products 0) gets 0.5. */
 int fastlbp_marginals(fastlbp_graph_t g, double *p1);
@@ -198,6 +214,61 @@ int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1);
 
 /* Resets every message to uniform (cold start). */
 int fastlbp_messages_reset(fastlbp_graph_t g);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Serving: continuous batching of queries (the interactive loop of Section 5.2.2 at scale)      */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct fastlbp_server *fastlbp_server_t;
+
+typedef struct fastlbp_server_options {
+    int32_t device;        /* HIP device ordinal; every submitted graph must live there */
+    int32_t precision;     /* FASTLBP_FP32 or FASTLBP_FP64; every submitted graph must use it */
+    int32_t max_active;    /* runs advanced side by side (one workgroup each), >= 1 */
+    int32_t step_iters;    /* iterations per step; requests join or leave between steps, >= 1 */
+    size_t memory_budget;  /* bytes of resident message state of the active graphs; 0 = 80% of the
+                              device's free memory at creation */
+} fastlbp_server_options;
+
+typedef struct fastlbp_server_stats {
+    int64_t completed;        /* requests finished successfully */
+    int64_t message_updates;  /* factor-to-variable updates of the finished requests */
+    int64_t steps;            /* steps (persistent launches) so far */
+    double busy_ms;           /* wall time spent in steps */
+    double p50_ms, p99_ms;    /* latency (submit to marginals ready) of the finished requests */
+    int32_t pending, active;  /* queue length and runs in flight right now */
+} fastlbp_server_stats;
+
+/* Defaults: device 0, FP32, 256 active runs, 2 iterations per step, budget 0 (80% of free). */
+void fastlbp_server_options_default(fastlbp_server_options *o);
+
+/* Starts a server with its own host thread and stream. Errors: E_INVALID_ARG, E_DEVICE. */
+int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *out);
+
+/* Queues a request: apply the n_ev clamps (values 0/1, -1 releases) to the graph's evidence, then
+ * run max_iters iterations at most (tol, damping as in fastlbp_run) from the graph's current
+ * messages (warm start). The handle belongs to the server until the request completes: the
+ * caller must not use it meanwhile. Requests on one handle run one after another, in order.
+ * *ticket identifies the request. Errors: E_INVALID_ARG (device or precision mismatch),
+ * E_TOO_LARGE (graph state above the memory budget), E_STATE (server shutting down). */
+int fastlbp_server_submit(fastlbp_server_t s, fastlbp_graph_t g, int32_t n_ev, const int32_t *ev_vars,
+                          const int8_t *ev_vals, int32_t max_iters, double tol, double damping, uint64_t *ticket);
+
+/* Returns 1 while the request is pending. When it is done: returns 0, copies the marginals into
+ * p1 [V] (may be NULL), its stats and its latency in ms (submit to marginals ready), and forgets
+ * the ticket; a failed request returns its error code once. Errors: E_INVALID_ARG (unknown ticket). */
+int fastlbp_server_poll(fastlbp_server_t s, uint64_t ticket, double *p1, fastlbp_run_stats *stats,
+                        double *latency_ms);
+
+/* As fastlbp_server_poll, but blocks until the request is done. */
+int fastlbp_server_wait(fastlbp_server_t s, uint64_t ticket, double *p1, fastlbp_run_stats *stats,
+                        double *latency_ms);
+
+/* Aggregate statistics of the server so far. */
+int fastlbp_server_get_stats(fastlbp_server_t s, fastlbp_server_stats *out);
+
+/* Stops the server: waits for the runs in flight, fails the queued requests with E_STATE. */
+void fastlbp_server_destroy(fastlbp_server_t s);
 
 /* Description of the last failure on this thread ("" if none). */
 const char *fastlbp_last_error(void);

@@ -46,6 +46,20 @@ class Options(ctypes.Structure):
                 ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("step_iters", ctypes.c_int32), ("memory_budget", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("message_updates", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("busy_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("pending", ctypes.c_int32), ("active", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("contradictions", ctypes.c_int64), ("levels", ctypes.c_int32), ("executor", ctypes.c_int32),
@@ -57,10 +71,13 @@ class RunStats(ctypes.Structure):
 
 
 EXPORTS = [
-    "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_destroy", "fastlbp_schedule_set",
+    "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_clone", "fastlbp_graph_destroy",
+    "fastlbp_run_batch", "fastlbp_schedule_set",
     "fastlbp_schedule_levels", "fastlbp_analyze_levels", "fastlbp_graph_validate", "fastlbp_evidence_set",
     "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
-    "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version",
+    "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version", "fastlbp_server_options_default",
+    "fastlbp_server_create", "fastlbp_server_submit", "fastlbp_server_poll", "fastlbp_server_wait",
+    "fastlbp_server_get_stats", "fastlbp_server_destroy",
 ]
 
 _lib = None
@@ -87,6 +104,8 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_options_default.argtypes = [ctypes.POINTER(Options)]
     lib.fastlbp_options_default.restype = None
     lib.fastlbp_graph_create.argtypes = [i32, i32, P, P, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.fastlbp_graph_clone.argtypes = [P, ctypes.POINTER(P)]
+    lib.fastlbp_run_batch.argtypes = [i32, P, i32, f64, f64, P]
     lib.fastlbp_graph_destroy.argtypes = [P]
     lib.fastlbp_graph_destroy.restype = None
     lib.fastlbp_schedule_set.argtypes = [P, i32, P, ctypes.POINTER(i32)]
@@ -104,8 +123,19 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_last_error.restype = ctypes.c_char_p
     lib.fastlbp_version.argtypes = []
     lib.fastlbp_version.restype = ctypes.c_char_p
+    lib.fastlbp_server_options_default.argtypes = [ctypes.POINTER(ServerOptions)]
+    lib.fastlbp_server_options_default.restype = None
+    lib.fastlbp_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+    lib.fastlbp_server_submit.argtypes = [P, P, i32, P, P, i32, f64, f64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fastlbp_server_poll.argtypes = [P, ctypes.c_uint64, P, ctypes.POINTER(RunStats), ctypes.POINTER(f64)]
+    lib.fastlbp_server_wait.argtypes = [P, ctypes.c_uint64, P, ctypes.POINTER(RunStats), ctypes.POINTER(f64)]
+    lib.fastlbp_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.fastlbp_server_destroy.argtypes = [P]
+    lib.fastlbp_server_destroy.restype = None
+    no_rc = ("fastlbp_options_default", "fastlbp_graph_destroy", "fastlbp_last_error", "fastlbp_version",
+             "fastlbp_server_options_default", "fastlbp_server_destroy")
     for name in EXPORTS:
-        if name not in ("fastlbp_options_default", "fastlbp_graph_destroy", "fastlbp_last_error", "fastlbp_version"):
+        if name not in no_rc:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -144,6 +174,15 @@ def analyze_levels(num_vars, fac_off, edge_var, edge_rank) -> tuple[np.ndarray, 
     n = ctypes.c_int32(0)
     _check(load().fastlbp_analyze_levels(int(num_vars), len(fo) - 1, _p(fo), _p(ev), _p(rk), _p(out), ctypes.byref(n)))
     return out, int(n.value)
+
+
+def run_batch(graphs, max_iters: int, tol: float = 0.0, damping: float = 0.0) -> list:
+    """Runs several handles side by side in one persistent launch (one workgroup each)."""
+    arr = (ctypes.c_void_p * len(graphs))(*[g._h.value for g in graphs])
+    st = (RunStats * len(graphs))()
+    _check(load().fastlbp_run_batch(len(graphs), ctypes.cast(arr, ctypes.c_void_p), int(max_iters), float(tol),
+                                    float(damping), ctypes.cast(st, ctypes.c_void_p)))
+    return [s.as_dict() for s in st]
 
 
 class _TorchAllocator:
@@ -219,6 +258,20 @@ class Graph:
         self._h = h
         self.precision = precision
         _LIVE.add(self)
+
+    def clone(self) -> "Graph":
+        """Another handle on the same graph (shared structure and schedule, own messages, no
+        evidence, own stream)."""
+        h = ctypes.c_void_p()
+        _check(load().fastlbp_graph_clone(self._h, ctypes.byref(h)))
+        g = Graph.__new__(Graph)
+        g._h = h
+        g._keep = self._keep
+        g.stream = self.stream
+        g.num_vars, g.num_edges, g.fac_type, g.fac_off = self.num_vars, self.num_edges, self.fac_type, self.fac_off
+        g.precision = self.precision
+        _LIVE.add(g)
+        return g
 
     @classmethod
     def from_workload(cls, w, **kw) -> "Graph":
@@ -297,3 +350,82 @@ class Graph:
 
     def messages_reset(self):
         _check(load().fastlbp_messages_reset(self._h))
+
+
+class Server:
+    """Continuous-batching query server (see include/fastlbp.h): requests on graph handles are
+    admitted between steps and advanced side by side, one workgroup per run."""
+
+    def __init__(self, precision: str = "fp32", device: int = 0, max_active: int = 256, step_iters: int = 2,
+                 memory_budget: int = 0):
+        lib = load()
+        o = ServerOptions()
+        lib.fastlbp_server_options_default(ctypes.byref(o))
+        o.device = int(device)
+        o.precision = {"fp64": FP64, "fp32": FP32}[precision]
+        o.max_active = int(max_active)
+        o.step_iters = int(step_iters)
+        o.memory_budget = int(memory_budget)
+        h = ctypes.c_void_p()
+        _check(lib.fastlbp_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._nv = {}
+        _LIVE_SERVERS.add(self)
+
+    def submit(self, graph: "Graph", ev_vars=(), ev_vals=(), max_iters: int = 100, tol: float = 0.0,
+               damping: float = 0.0) -> int:
+        v = np.ascontiguousarray(ev_vars, dtype=np.int32)
+        x = np.ascontiguousarray(ev_vals, dtype=np.int8)
+        if len(v) != len(x):
+            raise FastLBPError(E_INVALID_ARG, "vars and values differ in length")
+        t = ctypes.c_uint64(0)
+        _check(load().fastlbp_server_submit(self._h, graph._h, len(v), _p(v), _p(x), int(max_iters), float(tol),
+                                            float(damping), ctypes.byref(t)))
+        self._nv[t.value] = graph.num_vars
+        return t.value
+
+    def _collect(self, fn, ticket):
+        p1 = np.zeros(self._nv[ticket])
+        st = RunStats()
+        lat = ctypes.c_double(0.0)
+        rc = fn(self._h, ctypes.c_uint64(ticket), _p(p1), ctypes.byref(st), ctypes.byref(lat))
+        if rc == 1:
+            return None
+        self._nv.pop(ticket, None)
+        _check(rc)
+        return p1, st.as_dict(), lat.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (marginals, stats, latency_ms)."""
+        return self._collect(load().fastlbp_server_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._collect(load().fastlbp_server_wait, ticket)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(load().fastlbp_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().fastlbp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_LIVE_SERVERS: "weakref.WeakSet[Server]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_servers():
+    for s in list(_LIVE_SERVERS):
+        try:
+            s.close()
+        except Exception:
+            pass

@@ -35,13 +35,11 @@ struct HostGraph {
     // PRIOR factors folded per variable: finite LLR sum (bits) and counts of p = 1 / p = 0
     std::vector<double> prior_fin;
     std::vector<int32_t> prior_pos, prior_neg;
-    std::vector<int8_t> evidence;    // -1, 0, 1
     int32_t max_deg = 0;
     int64_t nonprior_edges = 0;
 
     void build(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
                const double *ep);
-    void phi(std::vector<Belief> &out) const;
 };
 
 // Work lists for one schedule. Levels without any non-PRIOR edge are not executed.
@@ -57,6 +55,8 @@ struct HostPlan {
     std::vector<int32_t> var_list[VB_COUNT];
     std::vector<int32_t> var_lvl_off[VB_COUNT];
     std::vector<int32_t> init_var[VB_COUNT];
+    // task records of the thread buckets, in the order of fac_list / var_list (12 / 8 int32 each)
+    std::vector<int32_t> frec, vrec;
     double bytes_per_iter = 0.0;   // algorithmic bytes of one iteration
     int64_t updates_per_iter = 0;  // non-PRIOR edges written per iteration
 

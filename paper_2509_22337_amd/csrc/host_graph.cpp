@@ -223,18 +223,6 @@ void HostGraph::build(int32_t V_, int32_t F_, const int64_t *off, const int32_t 
             else
                 prior_fin[v] += std::log2(p) - std::log2(1.0 - p);
         }
-    evidence.assign(V, -1);
-}
-
-void HostGraph::phi(std::vector<Belief> &out) const {
-    out.resize(V);
-    for (int32_t v = 0; v < V; ++v) {
-        Belief b;
-        b.fin = prior_fin[v];
-        b.npos = prior_pos[v] + (evidence[v] == 1 ? 1 : 0);
-        b.nneg = prior_neg[v] + (evidence[v] == 0 ? 1 : 0);
-        out[v] = b;
-    }
 }
 
 int factor_bucket(int deg) {
@@ -327,6 +315,30 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         init_var[b].clear();
     }
     for (int32_t v = 0; v < g.V; ++v) init_var[g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE].push_back(v);
+    // records: factor {b, d | type << 8 | active << 16, id, u0..u7, 0}; variable {v, row, degree, e0..e4}
+    frec.assign(fac_list[FB_THREAD].size() * 12, 0);
+    for (int32_t L = 0; L < exec_levels; ++L)
+        for (int32_t i = fac_lvl_off[FB_THREAD][L]; i < fac_lvl_off[FB_THREAD][L + 1]; ++i) {
+            int32_t a = fac_list[FB_THREAD][i];
+            int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
+            int32_t *r = &frec[size_t(i) * 12];
+            unsigned mask = 0;
+            for (int64_t k = 0; k < d; ++k)
+                if (edge_exec_level[b + k] == L) mask |= 1u << k;
+            r[0] = int32_t(b);
+            r[1] = int32_t(d) | (int32_t(g.fac_type[a]) << 8) | int32_t(mask << 16);
+            r[2] = a;
+            for (int k = 0; k < 8; ++k) r[3 + k] = k < d ? g.edge_var[b + k] : 0;
+        }
+    vrec.assign(var_list[VB_THREAD].size() * 8, 0);
+    for (size_t i = 0; i < var_list[VB_THREAD].size(); ++i) {
+        int32_t v = var_list[VB_THREAD][i];
+        int32_t *r = &vrec[i * 8];
+        r[0] = v;
+        r[1] = g.var_off[v];
+        r[2] = g.var_deg[v];
+        for (int j = 0; j < kVarRecEdges; ++j) r[3 + j] = j < g.var_deg[v] ? g.var_edge[g.var_off[v] + j] : 0;
+    }
 }
 
 }  // namespace fastlbp

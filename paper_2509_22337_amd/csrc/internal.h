@@ -1,0 +1,68 @@
+// Internal interface between the runtime (kernels, graph handles) and the serving loop.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "fastlbp.h"
+#include "layout.h"
+
+namespace fastlbp {
+
+// Device allocator: the caller's callbacks (e.g. a framework's caching allocator) or hipMalloc.
+struct Alloc {
+    void *(*fn_alloc)(size_t, void *) = nullptr;
+    void (*fn_free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+    void *get(size_t bytes) const {
+        if (bytes == 0) bytes = 16;
+        if (fn_alloc) return fn_alloc(bytes, ctx);
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void *p) const {
+        if (!p) return;
+        if (fn_free)
+            fn_free(p, ctx);
+        else
+            (void)hipFree(p);
+    }
+};
+
+struct OomError {};
+struct DeviceError {
+    std::string msg;
+};
+
+struct Launcher;
+
+void set_error(const std::string &msg);
+void clear_error();
+
+// The server drives runs in steps: step_begin resets a handle's run state (iteration 0) for a
+// run of max_iters; step_run advances n handles by up to `step` iterations in one persistent
+// launch (one workgroup per handle) and waits for it; read_state copies a handle's run state
+// to its pinned host mirror (graph_host_state).
+Launcher *launcher_create(int device, hipStream_t s, const Alloc &a);
+void launcher_destroy(Launcher *l);
+hipStream_t launcher_stream(Launcher *l);
+void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step);
+void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
+void read_state(fastlbp_graph *g, hipStream_t s);
+const RunState &graph_host_state(fastlbp_graph *g);
+void marginals_into(fastlbp_graph *g, double *p1);
+void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms);
+int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t *values);
+int graph_device(fastlbp_graph *g);
+int graph_precision(fastlbp_graph *g);
+size_t graph_state_bytes(fastlbp_graph *g);
+int32_t graph_num_vars(fastlbp_graph *g);
+void graph_sync(fastlbp_graph *g);
+
+}  // namespace fastlbp

@@ -170,11 +170,11 @@ struct Acc {
     unsigned int contra;
 };
 
-// Writes the new message of edge e (damping, residual, contradiction handling).
+// New stored value of a message from its unnormalised entries (o0, o1): contradiction handling,
+// damping against the old value, residual.
 template <class P, bool DAMP>
-__device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename P::V> &g, int32_t e,
-                                          typename P::S old, typename P::V o0, typename P::V o1, bool force_contra,
-                                          Acc &acc) {
+__device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S, typename P::V> &g, typename P::S old,
+                                                    typename P::V o0, typename P::V o1, bool force_contra, Acc &acc) {
     using S = typename P::S;
     using V = typename P::V;
     bool contra;
@@ -194,7 +194,14 @@ __device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename
     }
     double d = fabs(prob1((double)l) - prob1((double)old));
     acc.r = fmax(acc.r, d);
-    g.msg[e] = l;
+    return l;
+}
+
+template <class P, bool DAMP>
+__device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename P::V> &g, int32_t e,
+                                          typename P::S old, typename P::V o0, typename P::V o1, bool force_contra,
+                                          Acc &acc) {
+    g.msg[e] = finish_msg<P, DAMP>(g, old, o0, o1, force_contra, acc);
 }
 
 template <bool ALL_ACTIVE>
@@ -521,6 +528,148 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
         p.nneg += B.nneg;
         g.bel[v] = p;
     }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Record-based processing for the persistent executor. The host packs, per level, one record per
+// factor task with everything static already resolved (edge range, degree, type, the level's active
+// edges, variable ids) and one per variable task (row start, degree, first edge ids), so that a
+// thread issues all of a task's dynamic loads (messages, beliefs) at once.
+// ------------------------------------------------------------------------------------------------
+
+struct FacRec {
+    int4 r0;  // b, meta = d | type << 8 | active << 16, factor id, u0
+    int4 r1;  // u1 .. u4
+    int4 r2;  // u5 .. u7, unused
+};
+
+struct VarRec {
+    int4 r0;  // v, row start, degree, e0
+    int4 r1;  // e1 .. e4
+};
+
+// One factor of degree d <= 8 from values in registers: lo[k] the old message of edge b + k,
+// vf[k] its variable-to-factor message, nl[k] whether that is the null message. Bit k of `active`
+// selects the edges the level writes.
+template <class P, bool DAMP>
+__device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int d,
+                                             int32_t b, unsigned active, const Pair<typename P::V> &fp,
+                                             const typename P::S (&lo)[8], const typename P::S (&vf)[8],
+                                             const bool (&nl)[8], Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    if (type == T_NOT) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!((active >> k) & 1u)) continue;
+            V m0, m1;
+            P::leaf(-vf[1 - k], m0, m1);
+            store_msg<P, DAMP>(g, b + k, lo[k], m0, m1, nl[1 - k], acc);
+        }
+        return;
+    }
+    const int n = d - 1;
+    // head values, selected without dynamic register indexing
+    S vfh = (S)0, loh = (S)0;
+    bool nlh = false;
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k == n) {
+            vfh = vf[k];
+            loh = lo[k];
+            nlh = nl[k];
+        }
+    V my0 = P::zero(), my1 = P::zero();
+    if (!nlh) P::leaf(vfh, my0, my1);
+    HF<V> lf[7];
+    int nnull = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        if (k < n) {
+            lf[k] = identity<P>();
+            if (!nl[k]) {
+                V m0, m1;
+                P::leaf(vf[k], m0, m1);
+                Pair<V> ep = {P::zero(), P::one()};
+                if (type == T_NOISY_OR) ep = g.epar[b + k];
+                lf[k] = make_leaf<P>(type, m0, m1, ep);
+            } else {
+                ++nnull;
+            }
+        }
+    }
+    HF<V> pre = identity<P>();
+    if (type == T_NOISY_OR) pre = {fp.b, fp.a};  // leak
+    HF<V> tot = pre;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        if (k < n) tot = combine<P>(tot, lf[k]);
+    if ((active >> n) & 1u) {
+        V o0, o1;
+        head_msg<P>(type, tot, fp, o0, o1);
+        g.msg[b + n] = finish_msg<P, DAMP>(g, loh, o0, o1, nnull > 0, acc);
+    }
+    HF<V> sx[7];
+    HF<V> run = identity<P>();
+#pragma unroll
+    for (int k = 6; k >= 0; --k)
+        if (k < n) {
+            sx[k] = run;
+            run = combine<P>(lf[k], run);
+        }
+    run = pre;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        if (k < n) {
+            if ((active >> k) & 1u) {
+                HF<V> xo = combine<P>(run, sx[k]);
+                Pair<V> ep = {P::zero(), P::one()};
+                if (type == T_NOISY_OR) ep = g.epar[b + k];
+                V o0, o1;
+                input_msg<P>(type, xo, my0, my1, fp, ep, o0, o1);
+                int others_null = nnull - (nl[k] ? 1 : 0) + (nlh ? 1 : 0);
+                g.msg[b + k] = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
+            }
+            run = combine<P>(run, lf[k]);
+        }
+    }
+}
+
+template <class P, bool DAMP>
+__device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    const int32_t b = r.r0.x;
+    const int d = r.r0.y & 0xff, type = (r.r0.y >> 8) & 0xff;
+    const unsigned active = (unsigned)(r.r0.y >> 16) & 0xffu;
+    const int32_t u[8] = {r.r0.w, r.r1.x, r.r1.y, r.r1.z, r.r1.w, r.r2.x, r.r2.y, r.r2.z};
+    S lo[8], vf[8];
+    bool nl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        lo[k] = (S)0;
+        vf[k] = (S)0;
+        nl[k] = false;
+        if (k < d) {
+            lo[k] = g.msg[b + k];
+            vf[k] = v2f<P>(g.bel[u[k]], lo[k], nl[k]);
+        }
+    }
+    Pair<V> fp = {P::zero(), P::one()};
+    if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar[r.r0.z];
+    factor_local<P, DAMP>(g, type, d, b, active, fp, lo, vf, nl, acc);
+}
+
+template <class P>
+__device__ __forceinline__ void var_rec(const DevGraph<typename P::S, typename P::V> &g, const VarRec &r) {
+    const int32_t v = r.r0.x, start = r.r0.y, cnt = r.r0.z;
+    const int32_t e[kVarRecEdges] = {r.r0.w, r.r1.x, r.r1.y, r.r1.z, r.r1.w};
+    Belief B = g.phi[v];
+#pragma unroll
+    for (int j = 0; j < kVarRecEdges; ++j)
+        if (j < cnt) belief_add<P>(B, g.msg[e[j]]);
+    for (int32_t j = kVarRecEdges; j < cnt; ++j) belief_add<P>(B, g.msg[g.var_edge[start + j]]);
+    g.bel[v] = B;
 }
 
 }  // namespace fastlbp

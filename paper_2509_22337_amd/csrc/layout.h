@@ -38,6 +38,8 @@ struct RunState {
     int32_t max_iters;
     int32_t converged;
     double tol;
+    int32_t step_end;           // a launch of the persistent executor returns once iter reaches this
+    int32_t pad;
 };
 
 // Degree buckets. Factor degree d = inputs + head.
@@ -45,6 +47,7 @@ constexpr int kThreadMaxDeg = 8;     // one thread per factor
 constexpr int kWaveMaxDeg = 1025;    // one wavefront per factor: 64 lanes x 16 inputs + head
 constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 1024 x 16 + head
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
+constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record
 
 enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_COUNT = 3 };
 enum { VB_THREAD = 0, VB_WAVE = 1, VB_COUNT = 2 };
@@ -80,6 +83,11 @@ struct DevPlan {
     const int32_t *var_lvl_off[VB_COUNT];  // [num_levels+1]
     const int32_t *init_var[VB_COUNT];
     int32_t init_var_count[VB_COUNT];
+    // per-level task records of the thread buckets (persistent executor)
+    const void *frec;            // FacRec per factor task of the thread bucket
+    const int32_t *frec_off;     // [num_levels+1]
+    const void *vrec;            // VarRec per variable task of the thread bucket
+    const int32_t *vrec_off;     // [num_levels+1]
 };
 
 }  // namespace fastlbp

@@ -12,6 +12,7 @@
 
 #include "fastlbp.h"
 #include "host.h"
+#include "internal.h"
 #include "kernels.h"
 
 namespace fastlbp {
@@ -101,6 +102,7 @@ __global__ void k_run_init(RunState *st, int32_t max_iters, double tol) {
         st->max_iters = max_iters;
         st->converged = 0;
         st->tol = tol;
+        st->step_end = max_iters;
     }
 }
 
@@ -136,49 +138,76 @@ __global__ void k_marginals(const Belief *bel, int32_t V, double *out) {
     out[v] = p;
 }
 
-// One workgroup of NT threads runs the whole run: every iteration, every level, both phases, with
-// workgroup barriers between phases. Used when the levels are too narrow to fill the GPU. TEAMS
-// adds the wavefront- and workgroup-per-factor paths (plans with factors of degree > 8).
-template <class P, bool ALL, bool DAMP, bool TEAMS, int NT>
-__global__ __launch_bounds__(NT) void k_persistent(DevGraph<typename P::S, typename P::V> g, DevPlan plan,
-                                                   RunState *st) {
+// Descriptor of one run for the persistent executor: the graph view (structure + state pointers,
+// damping), the level plan and the run's state. A launch handles one descriptor per workgroup, so
+// many graphs (or many queries of one graph) run side by side in one launch.
+template <class P>
+struct RunDesc {
+    DevGraph<typename P::S, typename P::V> g;
+    DevPlan plan;
+    RunState *st;
+};
+
+// One workgroup of NT threads runs every level and iteration of one run, with workgroup barriers
+// between phases. Used when the levels are too narrow to fill the GPU. Thread tasks come as records
+// whose loads are issued one phase ahead (the variable records of a level while its factor phase
+// runs, the factor records of the next level while the variable phase runs), so each phase waits
+// for one round of dependent loads. TEAMS adds the wavefront- and workgroup-per-factor paths
+// (plans with factors of degree > 8). A launch returns when the run is done or its iteration
+// count reaches st->step_end, so a caller can advance many runs in steps.
+template <class P, bool DAMP, bool TEAMS, int NT>
+__global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
     using V = typename P::V;
     constexpr int NW = NT / 64;
     __shared__ TeamLds<V> lds;
     __shared__ double red_r[NW];
     __shared__ unsigned int red_c[NW];
     __shared__ int s_done;
+    const RunDesc<P> &D = descs[blockIdx.x];
+    const DevGraph<typename P::S, typename P::V> g = D.g;
+    const DevPlan plan = D.plan;
+    RunState *st = D.st;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const FacRec *frec = (const FacRec *)plan.frec;
+    const VarRec *vrec = (const VarRec *)plan.vrec;
+    const int32_t NL = plan.num_levels;
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
-    if (tid == 0) s_done = st->done;
+    if (tid == 0) s_done = st->done || st->iter >= st->step_end;
+    FacRec fr = {};
+    if (NL > 0 && plan.frec_off[0] + tid < plan.frec_off[1]) fr = frec[plan.frec_off[0] + tid];
     __syncthreads();
     while (!s_done) {
         Acc acc = {0.0, 0u};
-        for (int32_t L = 0; L < plan.num_levels; ++L) {
-            {
-                const int32_t *lst = plan.fac_list[FB_THREAD];
-                int32_t o0 = plan.fac_lvl_off[FB_THREAD][L], o1 = plan.fac_lvl_off[FB_THREAD][L + 1];
-                for (int32_t i = o0 + tid; i < o1; i += NT)
-                    factor_team<P, 1, kThreadMaxDeg - 1, ALL, DAMP>(g, lst[i], 0, L, acc, nullptr);
-            }
+        for (int32_t L = 0; L < NL; ++L) {
+            const int32_t f0 = plan.frec_off[L], f1 = plan.frec_off[L + 1];
+            const int32_t v0 = plan.vrec_off[L], v1 = plan.vrec_off[L + 1];
+            VarRec vr = {};
+            if (v0 + tid < v1) vr = vrec[v0 + tid];  // used by this level's variable phase
+            if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc);
+            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec[i], acc);
             if (TEAMS) {
                 const int32_t *lst = plan.fac_list[FB_WAVE];
                 int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
-                for (int32_t i = o0 + w; i < o1; i += NW) factor_team<P, 64, 16, ALL, DAMP>(g, lst[i], lane, L, acc, nullptr);
+                for (int32_t i = o0 + w; i < o1; i += NW)
+                    factor_team<P, 64, 16, false, DAMP>(g, lst[i], lane, L, acc, nullptr);
             }
             if (TEAMS) {
                 const int32_t *lst = plan.fac_list[FB_BLOCK];
                 int32_t o0 = plan.fac_lvl_off[FB_BLOCK][L], o1 = plan.fac_lvl_off[FB_BLOCK][L + 1];
                 for (int32_t i = o0; i < o1; ++i)
-                    factor_team<P, NT, (kBlockMaxDeg - 1) / NT, ALL, DAMP>(g, lst[i], tid, L, acc, &lds);
+                    factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, &lds);
             }
             __syncthreads();
             {
-                const int32_t *lst = plan.var_list[VB_THREAD];
-                int32_t o0 = plan.var_lvl_off[VB_THREAD][L], o1 = plan.var_lvl_off[VB_THREAD][L + 1];
-                for (int32_t i = o0 + tid; i < o1; i += NT) var_thread<P>(g, lst[i]);
+                // factor records of the next level (level 0 of the next iteration after the last)
+                const int32_t Ln = (L + 1 < NL) ? L + 1 : 0;
+                const int32_t n0 = plan.frec_off[Ln], n1 = plan.frec_off[Ln + 1];
+                fr = FacRec{};
+                if (n0 + tid < n1) fr = frec[n0 + tid];
             }
+            if (v0 + tid < v1) var_rec<P>(g, vr);
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec[i]);
             {
                 const int32_t *lst = plan.var_list[VB_WAVE];
                 int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
@@ -215,7 +244,7 @@ __global__ __launch_bounds__(NT) void k_persistent(DevGraph<typename P::S, typen
             } else if (st->iter >= st->max_iters) {
                 st->done = 1;
             }
-            s_done = st->done;
+            s_done = st->done || st->iter >= st->step_end;
         }
         __syncthreads();
     }
@@ -225,151 +254,190 @@ __global__ __launch_bounds__(NT) void k_persistent(DevGraph<typename P::S, typen
 // Device memory
 // ------------------------------------------------------------------------------------------------
 
-struct Alloc {
-    void *(*fn_alloc)(size_t, void *) = nullptr;
-    void (*fn_free)(void *, void *) = nullptr;
-    void *ctx = nullptr;
-    void *get(size_t bytes) {
-        if (bytes == 0) bytes = 16;
-        if (fn_alloc) return fn_alloc(bytes, ctx);
-        void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-        return p;
-    }
-    void put(void *p) {
-        if (!p) return;
-        if (fn_free)
-            fn_free(p, ctx);
-        else
-            (void)hipFree(p);
-    }
-};
-
-struct OomError {};
-struct DeviceError {
-    std::string msg;
-};
-
 #define HIPCHK(x)                                                                                          \
     do {                                                                                                   \
         hipError_t _e = (x);                                                                               \
         if (_e != hipSuccess) throw DeviceError{std::string(#x) + ": " + hipGetErrorString(_e)};           \
     } while (0)
 
+// A set of device allocations freed together.
+struct DevPool {
+    Alloc alloc;
+    std::vector<void *> owned;
+    size_t bytes = 0;
+    void *get(size_t n) {
+        void *p = alloc.get(n);
+        if (!p) throw OomError{};
+        owned.push_back(p);
+        bytes += n;
+        return p;
+    }
+    template <class T>
+    T *upload(const std::vector<T> &v, hipStream_t s) {
+        T *p = (T *)get(sizeof(T) * std::max<size_t>(v.size(), 1));
+        if (!v.empty()) {
+            HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));  // the host vector may die after return
+        }
+        return p;
+    }
+    void release() {
+        for (void *p : owned) alloc.put(p);
+        owned.clear();
+        bytes = 0;
+    }
+    ~DevPool() { release(); }
+};
+
+// Graph structure on the device: immutable after creation, shared by clones.
+struct Structure {
+    int device = 0;
+    int precision = FASTLBP_FP64;
+    HostGraph hg;
+    DevPool pool;
+    int32_t *fac_off = nullptr, *edge_var = nullptr, *var_off = nullptr, *var_edge = nullptr;
+    uint8_t *fac_type = nullptr;
+    void *fpar = nullptr, *epar = nullptr;
+    size_t msg_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
+    size_t val_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
+};
+
+// Level plan of one schedule on the device: immutable after schedule_set, shared by clones.
+struct Plan {
+    int kind = FASTLBP_SCHED_FLOODING;
+    HostPlan hp;
+    DevPool pool;
+    int32_t *edge_level = nullptr;
+    int32_t *fac_list[FB_COUNT] = {}, *fac_lvl_off[FB_COUNT] = {};
+    int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
+    int32_t *frec = nullptr, *vrec = nullptr;
+    bool teams() const { return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty(); }
+    DevPlan view() const {
+        DevPlan p;
+        p.num_levels = hp.exec_levels;
+        p.all_active = hp.all_active;
+        for (int b = 0; b < FB_COUNT; ++b) {
+            p.fac_list[b] = fac_list[b];
+            p.fac_lvl_off[b] = fac_lvl_off[b];
+        }
+        for (int b = 0; b < VB_COUNT; ++b) {
+            p.var_list[b] = var_list[b];
+            p.var_lvl_off[b] = var_lvl_off[b];
+            p.init_var[b] = init_var[b];
+            p.init_var_count[b] = int32_t(hp.init_var[b].size());
+        }
+        p.frec = frec;
+        p.frec_off = fac_lvl_off[FB_THREAD];
+        p.vrec = vrec;
+        p.vrec_off = var_lvl_off[VB_THREAD];
+        return p;
+    }
+};
+
+// Stream, descriptor buffer and events for persistent launches (one per handle, one per server).
+struct Launcher {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevPool pool;
+    void *desc = nullptr;
+    size_t desc_cap = 0;
+    std::vector<unsigned char> hdesc;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void init(hipStream_t s, const Alloc &a) {
+        pool.alloc = a;
+        if (s) {
+            stream = s;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        HIPCHK(hipEventCreate(&ev0));
+        HIPCHK(hipEventCreate(&ev1));
+    }
+    void *descs(size_t bytes) {
+        if (bytes > desc_cap) {
+            pool.release();
+            desc_cap = std::max<size_t>(bytes, 4096);
+            desc = pool.get(desc_cap);
+        }
+        return desc;
+    }
+    ~Launcher() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        pool.release();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
 }  // namespace fastlbp
 
 using namespace fastlbp;
 
-struct DevArrays {
-    // structure
-    int32_t *fac_off = nullptr, *edge_var = nullptr, *var_off = nullptr, *var_edge = nullptr, *edge_level = nullptr;
-    uint8_t *fac_type = nullptr;
-    void *fpar = nullptr, *epar = nullptr;
-    Belief *phi = nullptr, *bel = nullptr;
-    void *msg = nullptr;
-    RunState *state = nullptr;
-    double *marg = nullptr;
-    // plan
-    int32_t *fac_list[FB_COUNT] = {}, *fac_lvl_off[FB_COUNT] = {};
-    int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
-};
-
+// A graph handle: shared structure and plan, and its own message state, evidence and stream.
 struct fastlbp_graph {
     fastlbp_options opts;
     Alloc alloc;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int precision = FASTLBP_FP64;
-    HostGraph hg;
-    HostPlan plan;
-    int sched_kind = FASTLBP_SCHED_FLOODING;
-    DevArrays d;
-    std::vector<void *> owned;  // every device allocation
-    std::vector<void *> plan_owned;
-    // captured iterations for the LEVELS executor
+    std::shared_ptr<Structure> S;
+    std::shared_ptr<Plan> P;
+    std::vector<int8_t> evidence;
+    DevPool state;
+    Belief *phi = nullptr, *bel = nullptr;
+    void *msg = nullptr;
+    RunState *st = nullptr;
+    double *marg = nullptr;
+    Launcher L;
+    RunState *h_state = nullptr;  // pinned copy
+    // captured iterations of the LEVELS executor
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_iters = 0;
     double graph_damping = -1.0;
-    RunState *h_state = nullptr;  // pinned copy
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const Plan *graph_plan = nullptr;
     fastlbp_run_stats last{};
-    size_t msg_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
-    size_t val_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
 
-    void *dev(size_t bytes, bool plan_buf = false) {
-        void *p = alloc.get(bytes);
-        if (!p) throw OomError{};
-        (plan_buf ? plan_owned : owned).push_back(p);
-        return p;
-    }
-    template <class T>
-    T *upload(const std::vector<T> &v, bool plan_buf = false) {
-        T *p = (T *)dev(sizeof(T) * std::max<size_t>(v.size(), 1), plan_buf);
-        if (!v.empty()) {
-            HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream));
-            HIPCHK(hipStreamSynchronize(stream));  // the host vector may die after return
-        }
-        return p;
-    }
+    const HostGraph &hg() const { return S->hg; }
+    int precision() const { return S->precision; }
+    size_t state_bytes() const { return state.bytes; }
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
         graph_iters = 0;
+        graph_plan = nullptr;
     }
     ~fastlbp_graph() {
-        if (stream) (void)hipStreamSynchronize(stream);
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
         drop_graph();
-        for (void *p : owned) alloc.put(p);
-        for (void *p : plan_owned) alloc.put(p);
+        state.release();
         if (h_state) (void)hipHostFree(h_state);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
-
-    template <class P>
-    DevGraph<typename P::S, typename P::V> view(double damping) const {
-        DevGraph<typename P::S, typename P::V> g;
-        g.num_vars = hg.V;
-        g.num_edges = int32_t(hg.E);
-        g.fac_off = d.fac_off;
-        g.edge_var = d.edge_var;
-        g.fac_type = d.fac_type;
-        g.fpar = (const Pair<typename P::V> *)d.fpar;
-        g.epar = (const Pair<typename P::V> *)d.epar;
-        g.var_off = d.var_off;
-        g.var_edge = d.var_edge;
-        g.phi = d.phi;
-        g.bel = d.bel;
-        g.msg = (typename P::S *)d.msg;
-        g.edge_level = d.edge_level;
-        if (precision == FASTLBP_FP32) {
-            g.damp_old = (typename P::V)(damping > 0 ? std::log2(damping) : -INFINITY);
-            g.damp_new = (typename P::V)std::log2(1.0 - damping);
+    template <class PP>
+    DevGraph<typename PP::S, typename PP::V> view(double damping) const {
+        DevGraph<typename PP::S, typename PP::V> g;
+        g.num_vars = S->hg.V;
+        g.num_edges = int32_t(S->hg.E);
+        g.fac_off = S->fac_off;
+        g.edge_var = S->edge_var;
+        g.fac_type = S->fac_type;
+        g.fpar = (const Pair<typename PP::V> *)S->fpar;
+        g.epar = (const Pair<typename PP::V> *)S->epar;
+        g.var_off = S->var_off;
+        g.var_edge = S->var_edge;
+        g.phi = phi;
+        g.bel = bel;
+        g.msg = (typename PP::S *)msg;
+        g.edge_level = P->edge_level;
+        if (precision() == FASTLBP_FP32) {
+            g.damp_old = (typename PP::V)(damping > 0 ? std::log2(damping) : -INFINITY);
+            g.damp_new = (typename PP::V)std::log2(1.0 - damping);
         } else {
-            g.damp_old = (typename P::V)damping;
-            g.damp_new = (typename P::V)(1.0 - damping);
+            g.damp_old = (typename PP::V)damping;
+            g.damp_new = (typename PP::V)(1.0 - damping);
         }
         return g;
-    }
-    DevPlan dplan() const {
-        DevPlan p;
-        p.num_levels = plan.exec_levels;
-        p.all_active = plan.all_active;
-        for (int b = 0; b < FB_COUNT; ++b) {
-            p.fac_list[b] = d.fac_list[b];
-            p.fac_lvl_off[b] = d.fac_lvl_off[b];
-        }
-        for (int b = 0; b < VB_COUNT; ++b) {
-            p.var_list[b] = d.var_list[b];
-            p.var_lvl_off[b] = d.var_lvl_off[b];
-            p.init_var[b] = d.init_var[b];
-            p.init_var_count[b] = int32_t(plan.init_var[b].size());
-        }
-        return p;
     }
 };
 
@@ -395,78 +463,112 @@ static Pair<V> param_pair(double p, bool logd) {
 }
 
 template <class V>
-static void upload_params(fastlbp_graph *g, bool logd) {
-    std::vector<Pair<V>> fp(std::max(g->hg.F, 1)), ep(std::max<int64_t>(g->hg.E, 1));
-    for (int32_t a = 0; a < g->hg.F; ++a) fp[a] = param_pair<V>(g->hg.fac_param[a], logd);
-    for (int64_t e = 0; e < g->hg.E; ++e) ep[e] = param_pair<V>(g->hg.edge_param[e], logd);
-    g->d.fpar = g->upload(fp);
-    g->d.epar = g->upload(ep);
+static void upload_params(Structure &S, hipStream_t s, bool logd) {
+    std::vector<Pair<V>> fp(std::max(S.hg.F, 1)), ep(std::max<int64_t>(S.hg.E, 1));
+    for (int32_t a = 0; a < S.hg.F; ++a) fp[a] = param_pair<V>(S.hg.fac_param[a], logd);
+    for (int64_t e = 0; e < S.hg.E; ++e) ep[e] = param_pair<V>(S.hg.edge_param[e], logd);
+    S.fpar = S.pool.upload(fp, s);
+    S.epar = S.pool.upload(ep, s);
 }
 
-static void upload_plan(fastlbp_graph *g) {
-    HIPCHK(hipStreamSynchronize(g->stream));
-    for (void *p : g->plan_owned) g->alloc.put(p);
-    g->plan_owned.clear();
-    g->drop_graph();
-    g->d.edge_level = g->upload(g->plan.edge_exec_level, true);
+static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, hipStream_t s, int kind,
+                                       const int32_t *rank) {
+    auto P = std::make_shared<Plan>();
+    P->pool.alloc = alloc;
+    P->kind = kind;
+    std::vector<int32_t> level;
+    int32_t n = analyze_levels(S.hg.V, S.hg.F, S.hg.fac_off.data(), S.hg.edge_var.data(),
+                               kind == FASTLBP_SCHED_FLOODING ? nullptr : rank, level);
+    P->hp.build(S.hg, level, n, kind == FASTLBP_SCHED_FLOODING, int(S.msg_bytes()), int(2 * S.val_bytes()));
+    P->edge_level = P->pool.upload(P->hp.edge_exec_level, s);
     for (int b = 0; b < FB_COUNT; ++b) {
-        g->d.fac_list[b] = g->upload(g->plan.fac_list[b], true);
-        g->d.fac_lvl_off[b] = g->upload(g->plan.fac_lvl_off[b], true);
+        P->fac_list[b] = P->pool.upload(P->hp.fac_list[b], s);
+        P->fac_lvl_off[b] = P->pool.upload(P->hp.fac_lvl_off[b], s);
     }
     for (int b = 0; b < VB_COUNT; ++b) {
-        g->d.var_list[b] = g->upload(g->plan.var_list[b], true);
-        g->d.var_lvl_off[b] = g->upload(g->plan.var_lvl_off[b], true);
-        g->d.init_var[b] = g->upload(g->plan.init_var[b], true);
+        P->var_list[b] = P->pool.upload(P->hp.var_list[b], s);
+        P->var_lvl_off[b] = P->pool.upload(P->hp.var_lvl_off[b], s);
+        P->init_var[b] = P->pool.upload(P->hp.init_var[b], s);
     }
-    HIPCHK(hipStreamSynchronize(g->stream));
+    P->frec = P->pool.upload(P->hp.frec, s);
+    P->vrec = P->pool.upload(P->hp.vrec, s);
+    return P;
 }
 
 static void upload_phi(fastlbp_graph *g) {
     std::vector<Belief> phi;
-    g->hg.phi(phi);
+    const HostGraph &hg = g->hg();
+    phi.resize(hg.V);
+    for (int32_t v = 0; v < hg.V; ++v) {
+        Belief b;
+        b.fin = hg.prior_fin[v];
+        b.npos = hg.prior_pos[v] + (g->evidence[v] == 1 ? 1 : 0);
+        b.nneg = hg.prior_neg[v] + (g->evidence[v] == 0 ? 1 : 0);
+        phi[v] = b;
+    }
     if (phi.empty()) return;
-    HIPCHK(hipMemcpyAsync(g->d.phi, phi.data(), sizeof(Belief) * phi.size(), hipMemcpyHostToDevice, g->stream));
-    HIPCHK(hipStreamSynchronize(g->stream));
+    HIPCHK(hipMemcpyAsync(g->phi, phi.data(), sizeof(Belief) * phi.size(), hipMemcpyHostToDevice, g->L.stream));
+    HIPCHK(hipStreamSynchronize(g->L.stream));
+}
+
+// Allocates the handle's state (messages uniform, beliefs, phi from its evidence, run state).
+static void alloc_state(fastlbp_graph *g) {
+    const HostGraph &hg = g->hg();
+    g->state.alloc = g->alloc;
+    size_t mb = g->S->msg_bytes() * std::max<int64_t>(hg.E, 1);
+    g->phi = (Belief *)g->state.get(sizeof(Belief) * std::max(hg.V, 1));
+    g->bel = (Belief *)g->state.get(sizeof(Belief) * std::max(hg.V, 1));
+    g->msg = g->state.get(mb);
+    g->st = (RunState *)g->state.get(sizeof(RunState));
+    g->marg = (double *)g->state.get(sizeof(double) * std::max(hg.V, 1));
+    HIPCHK(hipMemsetAsync(g->msg, 0, mb, g->L.stream));
+    HIPCHK(hipMemsetAsync(g->bel, 0, sizeof(Belief) * std::max(hg.V, 1), g->L.stream));
+    HIPCHK(hipMemsetAsync(g->st, 0, sizeof(RunState), g->L.stream));
+    upload_phi(g);
 }
 
 // Recompute every belief from phi and the current messages.
-template <class P>
-static void launch_init_beliefs(fastlbp_graph *g, const DevGraph<typename P::S, typename P::V> &dg) {
-    int32_t n0 = int32_t(g->plan.init_var[VB_THREAD].size()), n1 = int32_t(g->plan.init_var[VB_WAVE].size());
-    if (n0) k_var_thread<P><<<grid_for(n0, 256), 256, 0, g->stream>>>(dg, g->d.init_var[VB_THREAD], n0, nullptr);
-    if (n1) k_var_wave<P><<<grid_for(n1, 4), 256, 0, g->stream>>>(dg, g->d.init_var[VB_WAVE], n1, nullptr);
+template <class PP>
+static void launch_init_beliefs(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg) {
+    const HostPlan &hp = g->P->hp;
+    int32_t n0 = int32_t(hp.init_var[VB_THREAD].size()), n1 = int32_t(hp.init_var[VB_WAVE].size());
+    if (n0) k_var_thread<PP><<<grid_for(n0, 256), 256, 0, g->L.stream>>>(dg, g->P->init_var[VB_THREAD], n0, nullptr);
+    if (n1) k_var_wave<PP><<<grid_for(n1, 4), 256, 0, g->L.stream>>>(dg, g->P->init_var[VB_WAVE], n1, nullptr);
     HIPCHK(hipGetLastError());
 }
 
 // One iteration of the LEVELS executor: for every level, the factor phase then the variable phase.
-template <class P, bool ALL, bool DAMP>
-static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename P::S, typename P::V> &dg) {
-    const HostPlan &pl = g->plan;
+template <class PP, bool ALL, bool DAMP>
+static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg) {
+    const HostPlan &pl = g->P->hp;
+    const Plan &P = *g->P;
+    hipStream_t s = g->L.stream;
     for (int32_t L = 0; L < pl.exec_levels; ++L) {
         int32_t o, n;
         o = pl.fac_lvl_off[FB_THREAD][L];
         n = pl.fac_lvl_off[FB_THREAD][L + 1] - o;
-        if (n) k_fac_thread<P, ALL, DAMP><<<grid_for(n, 256), 256, 0, g->stream>>>(dg, g->d.fac_list[FB_THREAD] + o, n, L, g->d.state);
+        if (n) k_fac_thread<PP, ALL, DAMP><<<grid_for(n, 256), 256, 0, s>>>(dg, P.fac_list[FB_THREAD] + o, n, L, g->st);
         o = pl.fac_lvl_off[FB_WAVE][L];
         n = pl.fac_lvl_off[FB_WAVE][L + 1] - o;
-        if (n) k_fac_wave<P, ALL, DAMP><<<grid_for(n, 4), 256, 0, g->stream>>>(dg, g->d.fac_list[FB_WAVE] + o, n, L, g->d.state);
+        if (n) k_fac_wave<PP, ALL, DAMP><<<grid_for(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
         o = pl.fac_lvl_off[FB_BLOCK][L];
         n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
         if (n)
-            k_fac_block<P, ALL, DAMP, block_threads<P>()><<<std::min(n, 4096), block_threads<P>(), 0, g->stream>>>(
-                dg, g->d.fac_list[FB_BLOCK] + o, n, L, g->d.state);
+            k_fac_block<PP, ALL, DAMP, block_threads<PP>()><<<std::min(n, 4096), block_threads<PP>(), 0, s>>>(
+                dg, P.fac_list[FB_BLOCK] + o, n, L, g->st);
         o = pl.var_lvl_off[VB_THREAD][L];
         n = pl.var_lvl_off[VB_THREAD][L + 1] - o;
-        if (n) k_var_thread<P><<<grid_for(n, 256), 256, 0, g->stream>>>(dg, g->d.var_list[VB_THREAD] + o, n, g->d.state);
+        if (n) k_var_thread<PP><<<grid_for(n, 256), 256, 0, s>>>(dg, P.var_list[VB_THREAD] + o, n, g->st);
         o = pl.var_lvl_off[VB_WAVE][L];
         n = pl.var_lvl_off[VB_WAVE][L + 1] - o;
-        if (n) k_var_wave<P><<<grid_for(n, 4), 256, 0, g->stream>>>(dg, g->d.var_list[VB_WAVE] + o, n, g->d.state);
+        if (n) k_var_wave<PP><<<grid_for(n, 4), 256, 0, s>>>(dg, P.var_list[VB_WAVE] + o, n, g->st);
     }
-    k_finalize<<<1, 64, 0, g->stream>>>(g->d.state);
+    k_finalize<<<1, 64, 0, s>>>(g->st);
 }
 
 // Workgroup size of the persistent executor: 1024 threads for float32, 512 for float64 (whose
-// factor code needs up to 256 registers). FASTLBP_PERSISTENT_THREADS=512|1024 overrides.
+// factor code needs more than the 128 registers a 1024-thread workgroup allows).
+// FASTLBP_PERSISTENT_THREADS=512|1024 overrides.
 static int persistent_threads(int precision) {
     const char *e = std::getenv("FASTLBP_PERSISTENT_THREADS");
     if (e && (std::atoi(e) == 512 || std::atoi(e) == 1024)) return std::atoi(e);
@@ -477,70 +579,127 @@ static int choose_executor(const fastlbp_graph *g) {
     int ex = g->opts.executor;
     if (ex == FASTLBP_EXEC_LEVELS || ex == FASTLBP_EXEC_PERSISTENT) return ex;
     // one workgroup keeps up with a level of a few thousand edges; wider levels need the GPU
-    if (g->plan.max_level_edges <= 8192 && g->hg.nonprior_edges <= (int64_t(4) << 20)) return FASTLBP_EXEC_PERSISTENT;
+    if (g->P->hp.max_level_edges <= 8192 && g->hg().nonprior_edges <= (int64_t(4) << 20)) return FASTLBP_EXEC_PERSISTENT;
     return FASTLBP_EXEC_LEVELS;
 }
 
-template <class P, bool ALL, bool DAMP>
-static void run_impl(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec) {
-    auto dg = g->view<P>(damping);
-    k_run_init<<<1, 64, 0, g->stream>>>(g->d.state, max_iters, tol);
+template <class PP, bool ALL, bool DAMP>
+static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping) {
+    auto dg = g->view<PP>(damping);
+    hipStream_t s = g->L.stream;
+    k_run_init<<<1, 64, 0, s>>>(g->st, max_iters, tol);
     HIPCHK(hipGetLastError());
-    if (exec == FASTLBP_EXEC_PERSISTENT) {
-        // the variant without wavefront/workgroup factor code needs fewer registers
-        bool teams = !g->plan.fac_list[FB_WAVE].empty() || !g->plan.fac_list[FB_BLOCK].empty();
-        // float64 factor code needs more than the 128 registers a 1024-thread workgroup allows
-        int nt = persistent_threads(g->precision);
-        if (teams && nt == 1024)
-            k_persistent<P, ALL, DAMP, true, 1024><<<1, 1024, 0, g->stream>>>(dg, g->dplan(), g->d.state);
-        else if (teams)
-            k_persistent<P, ALL, DAMP, true, 512><<<1, 512, 0, g->stream>>>(dg, g->dplan(), g->d.state);
-        else if (nt == 1024)
-            k_persistent<P, ALL, DAMP, false, 1024><<<1, 1024, 0, g->stream>>>(dg, g->dplan(), g->d.state);
-        else
-            k_persistent<P, ALL, DAMP, false, 512><<<1, 512, 0, g->stream>>>(dg, g->dplan(), g->d.state);
-        HIPCHK(hipGetLastError());
-        return;
-    }
-    launch_init_beliefs<P>(g, dg);
+    launch_init_beliefs<PP>(g, dg);
     if (max_iters <= 0) return;
     // iterations per replay: enough to amortise the launch, few enough to stop soon after
     // convergence (kernels of finished iterations return at once)
-    int per_iter_kernels = 1 + 2 * std::max(1, g->plan.exec_levels);
+    int per_iter_kernels = 1 + 2 * std::max(1, g->P->hp.exec_levels);
     int K = std::max(1, std::min(32, 2048 / per_iter_kernels));
     K = std::min(K, max_iters);
     bool use_graph = g->opts.use_graph != 0;
-    if (use_graph && (!g->gexec || g->graph_iters != K || g->graph_damping != damping)) {
+    if (use_graph && (!g->gexec || g->graph_iters != K || g->graph_damping != damping || g->graph_plan != g->P.get())) {
         g->drop_graph();
-        HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < K; ++k) enqueue_iteration<P, ALL, DAMP>(g, dg);
-        HIPCHK(hipStreamEndCapture(g->stream, &g->graph));
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+        HIPCHK(hipStreamEndCapture(s, &g->graph));
         HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
         g->graph_iters = K;
         g->graph_damping = damping;
+        g->graph_plan = g->P.get();
     }
     int done_iters = 0;
     while (true) {
         if (use_graph)
-            HIPCHK(hipGraphLaunch(g->gexec, g->stream));
+            HIPCHK(hipGraphLaunch(g->gexec, s));
         else
-            for (int k = 0; k < K; ++k) enqueue_iteration<P, ALL, DAMP>(g, dg);
+            for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
         HIPCHK(hipGetLastError());
         done_iters += K;
         if (done_iters >= max_iters) break;
-        HIPCHK(hipMemcpyAsync(g->h_state, g->d.state, sizeof(RunState), hipMemcpyDeviceToHost, g->stream));
-        HIPCHK(hipStreamSynchronize(g->stream));
+        HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
         if (g->h_state->done) break;
     }
 }
 
-template <class P>
+// One persistent launch over n runs (one workgroup each) on `lc`'s stream. Every run advances
+// until it is done or its iteration count reaches its step_end.
+template <class PP>
+static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping) {
+    if (n <= 0) return;
+    bool teams = false, damp = false;
+    for (int i = 0; i < n; ++i) {
+        teams = teams || gs[i]->P->teams();
+        damp = damp || damping[i] > 0.0;
+    }
+    size_t bytes = sizeof(RunDesc<PP>) * size_t(n);
+    void *d = lc.descs(bytes);
+    lc.hdesc.resize(bytes);
+    RunDesc<PP> *h = (RunDesc<PP> *)lc.hdesc.data();
+    for (int i = 0; i < n; ++i) {
+        h[i].g = gs[i]->view<PP>(damping[i]);
+        h[i].plan = gs[i]->P->view();
+        h[i].st = gs[i]->st;
+    }
+    HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, lc.stream));
+    const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
+    int nt = persistent_threads(gs[0]->precision());
+    hipStream_t s = lc.stream;
+#define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, 0, s>>>(dd)
+    if (nt == 1024) {
+        if (damp && teams) FASTLBP_LAUNCH(true, true, 1024);
+        else if (damp) FASTLBP_LAUNCH(true, false, 1024);
+        else if (teams) FASTLBP_LAUNCH(false, true, 1024);
+        else FASTLBP_LAUNCH(false, false, 1024);
+    } else {
+        if (damp && teams) FASTLBP_LAUNCH(true, true, 512);
+        else if (damp) FASTLBP_LAUNCH(true, false, 512);
+        else if (teams) FASTLBP_LAUNCH(false, true, 512);
+        else FASTLBP_LAUNCH(false, false, 512);
+    }
+#undef FASTLBP_LAUNCH
+    HIPCHK(hipGetLastError());
+    // the host staging buffer may be rewritten by the next call
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+__global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int32_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->rbits = 0ull;
+        st->contra = 0ull;
+        st->iter = 0;
+        st->done = max_iters <= 0 ? 1 : 0;
+        st->last_r = 0.0;
+        st->max_iters = max_iters;
+        st->converged = 0;
+        st->tol = tol;
+        st->step_end = step;
+    }
+}
+
+__global__ void k_step_advance(RunState *st, int32_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->step_end = st->iter + step;
+}
+
+template <class PP, bool ALL, bool DAMP>
+static void run_single(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec) {
+    if (exec == FASTLBP_EXEC_LEVELS) {
+        run_levels<PP, ALL, DAMP>(g, max_iters, tol, damping);
+        return;
+    }
+    k_run_init_step<<<1, 64, 0, g->L.stream>>>(g->st, max_iters, tol, max_iters);
+    HIPCHK(hipGetLastError());
+    fastlbp_graph *one[1] = {g};
+    launch_persistent<PP>(g->L, 1, one, &damping);
+}
+
+template <class PP>
 static void run_dispatch(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec) {
-    bool all = g->plan.all_active != 0, damp = damping > 0.0;
-    if (all && damp) run_impl<P, true, true>(g, max_iters, tol, damping, exec);
-    if (all && !damp) run_impl<P, true, false>(g, max_iters, tol, damping, exec);
-    if (!all && damp) run_impl<P, false, true>(g, max_iters, tol, damping, exec);
-    if (!all && !damp) run_impl<P, false, false>(g, max_iters, tol, damping, exec);
+    bool all = g->P->hp.all_active != 0, damp = damping > 0.0;
+    if (all && damp) run_single<PP, true, true>(g, max_iters, tol, damping, exec);
+    if (all && !damp) run_single<PP, true, false>(g, max_iters, tol, damping, exec);
+    if (!all && damp) run_single<PP, false, true>(g, max_iters, tol, damping, exec);
+    if (!all && !damp) run_single<PP, false, false>(g, max_iters, tol, damping, exec);
 }
 
 static int device_error(const DeviceError &e) {
@@ -548,17 +707,81 @@ static int device_error(const DeviceError &e) {
     return FASTLBP_E_DEVICE;
 }
 
-static int set_schedule(fastlbp_graph *g, int kind, const int32_t *rank) {
-    std::vector<int32_t> level;
-    int32_t n = analyze_levels(g->hg.V, g->hg.F, g->hg.fac_off.data(), g->hg.edge_var.data(),
-                               kind == FASTLBP_SCHED_FLOODING ? nullptr : rank, level);
-    HostPlan p;
-    p.build(g->hg, level, n, kind == FASTLBP_SCHED_FLOODING, int(g->msg_bytes()), int(2 * g->val_bytes()));
-    g->plan = std::move(p);
-    g->sched_kind = kind;
-    upload_plan(g);
+static void fill_stats(fastlbp_graph *g, int exec, float ms, fastlbp_run_stats &s) {
+    s = fastlbp_run_stats{};
+    s.iterations = g->h_state->iter;
+    s.converged = g->h_state->converged;
+    s.residual = g->h_state->last_r;
+    s.contradictions = (int64_t)g->h_state->contra;
+    s.levels = g->P->hp.num_levels;
+    s.executor = exec;
+    s.algorithmic_bytes_per_iter = g->P->hp.bytes_per_iter;
+    s.device_ms = ms;
+    s.message_updates = g->P->hp.updates_per_iter * int64_t(s.iterations);
+    g->last = s;
+}
+
+// ---- used by the server ----------------------------------------------------------------------
+
+void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step) {
+    k_run_init_step<<<1, 64, 0, g->L.stream>>>(g->st, max_iters, tol, step);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(g->L.stream));
+}
+
+void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
+    for (int i = 0; i < n; ++i) k_step_advance<<<1, 64, 0, lc.stream>>>(gs[i]->st, step);
+    HIPCHK(hipGetLastError());
+    if (gs[0]->precision() == FASTLBP_FP32)
+        launch_persistent<PolLog32>(lc, n, gs, damping);
+    else
+        launch_persistent<PolLin64>(lc, n, gs, damping);
+}
+
+void read_state(fastlbp_graph *g, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void marginals_into(fastlbp_graph *g, double *p1) {
+    if (g->hg().V == 0) return;
+    if (g->precision() == FASTLBP_FP32)
+        launch_init_beliefs<PolLog32>(g, g->view<PolLog32>(0.0));
+    else
+        launch_init_beliefs<PolLin64>(g, g->view<PolLin64>(0.0));
+    k_marginals<<<grid_for(g->hg().V, 256), 256, 0, g->L.stream>>>(g->bel, g->hg().V, g->marg);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(p1, g->marg, sizeof(double) * g->hg().V, hipMemcpyDeviceToHost, g->L.stream));
+    HIPCHK(hipStreamSynchronize(g->L.stream));
+}
+
+void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms) { fill_stats(g, FASTLBP_EXEC_PERSISTENT, ms, s); }
+
+int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t *values) {
+    for (int32_t i = 0; i < n; ++i)
+        if (vars[i] < 0 || vars[i] >= g->hg().V || values[i] < -1 || values[i] > 1) {
+            set_error("evidence entry " + std::to_string(i) + " out of range");
+            return FASTLBP_E_INVALID_ARG;
+        }
+    for (int32_t i = 0; i < n; ++i) g->evidence[vars[i]] = values[i];
+    upload_phi(g);
     return FASTLBP_OK;
 }
+
+Launcher *launcher_create(int device, hipStream_t s, const Alloc &a) {
+    HIPCHK(hipSetDevice(device));
+    auto *l = new Launcher();
+    l->init(s, a);
+    return l;
+}
+void launcher_destroy(Launcher *l) { delete l; }
+hipStream_t launcher_stream(Launcher *l) { return l->stream; }
+int graph_device(fastlbp_graph *g) { return g->opts.device; }
+int graph_precision(fastlbp_graph *g) { return g->precision(); }
+size_t graph_state_bytes(fastlbp_graph *g) { return g->state_bytes(); }
+int32_t graph_num_vars(fastlbp_graph *g) { return g->hg().V; }
+const RunState &graph_host_state(fastlbp_graph *g) { return *g->h_state; }
+void graph_sync(fastlbp_graph *g) { HIPCHK(hipStreamSynchronize(g->L.stream)); }
 
 }  // namespace fastlbp
 
@@ -578,22 +801,9 @@ void fastlbp_options_default(fastlbp_options *o) {
     o->use_graph = 1;
 }
 
-const char *fastlbp_version(void) { return "fastlbp-mi355x 0.1 (gfx950)"; }
+const char *fastlbp_version(void) { return "fastlbp-mi355x 0.2 (gfx950)"; }
 
-int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
-                         const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
-                         const double *edge_params, const fastlbp_options *opts, fastlbp_graph_t *out) {
-    clear_error();
-    if (!out) {
-        set_error("out is NULL");
-        return FASTLBP_E_INVALID_ARG;
-    }
-    *out = nullptr;
-    int rc = validate_graph(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
-    if (rc) return rc;
-    fastlbp_options o;
-    fastlbp_options_default(&o);
-    if (opts) o = *opts;
+static int check_options(const fastlbp_options &o) {
     if (o.precision != FASTLBP_FP64 && o.precision != FASTLBP_FP32) {
         set_error("precision must be FASTLBP_FP64 or FASTLBP_FP32");
         return FASTLBP_E_INVALID_ARG;
@@ -616,51 +826,74 @@ int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *f
         set_error("device ordinal out of range");
         return FASTLBP_E_INVALID_ARG;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o.device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipGetDeviceProperties failed");
+        return FASTLBP_E_DEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error(std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+        return FASTLBP_E_DEVICE;
+    }
+    return FASTLBP_OK;
+}
+
+// Common tail of create and clone: launcher, pinned state, device state.
+static int finish_handle(fastlbp_graph *g) {
+    HIPCHK(hipSetDevice(g->opts.device));
+    g->L.init((hipStream_t)g->opts.stream, g->alloc);
+    HIPCHK(hipHostMalloc((void **)&g->h_state, sizeof(RunState), hipHostMallocDefault));
+    alloc_state(g);
+    return FASTLBP_OK;
+}
+
+int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                         const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
+                         const double *edge_params, const fastlbp_options *opts, fastlbp_graph_t *out) {
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    int rc = validate_graph(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
+    if (rc) return rc;
+    fastlbp_options o;
+    fastlbp_options_default(&o);
+    if (opts) o = *opts;
+    rc = check_options(o);
+    if (rc) return rc;
     std::unique_ptr<fastlbp_graph> g(new fastlbp_graph());
     g->opts = o;
-    g->precision = o.precision;
     g->alloc.fn_alloc = o.alloc;
     g->alloc.fn_free = o.free;
     g->alloc.ctx = o.alloc_ctx;
     try {
         HIPCHK(hipSetDevice(o.device));
-        hipDeviceProp_t prop;
-        HIPCHK(hipGetDeviceProperties(&prop, o.device));
-        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-            set_error(std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
-            return FASTLBP_E_DEVICE;
-        }
-        if (o.stream) {
-            g->stream = (hipStream_t)o.stream;
-        } else {
-            HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-            g->own_stream = true;
-        }
-        HIPCHK(hipEventCreate(&g->ev0));
-        HIPCHK(hipEventCreate(&g->ev1));
-        HIPCHK(hipHostMalloc((void **)&g->h_state, sizeof(RunState), hipHostMallocDefault));
-        g->hg.build(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
-        HostGraph &hg = g->hg;
+        g->L.init((hipStream_t)o.stream, g->alloc);
+        hipStream_t s = g->L.stream;
+        auto S = std::make_shared<Structure>();
+        S->device = o.device;
+        S->precision = o.precision;
+        S->pool.alloc = g->alloc;
+        S->hg.build(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
+        const HostGraph &hg = S->hg;
         std::vector<int32_t> off32(hg.fac_off.begin(), hg.fac_off.end());
-        g->d.fac_off = g->upload(off32);
-        g->d.edge_var = g->upload(hg.edge_var);
-        g->d.fac_type = g->upload(hg.fac_type);
-        g->d.var_off = g->upload(hg.var_off);
-        g->d.var_edge = g->upload(hg.var_edge);
-        if (g->precision == FASTLBP_FP32)
-            upload_params<float>(g.get(), true);
+        S->fac_off = S->pool.upload(off32, s);
+        S->edge_var = S->pool.upload(hg.edge_var, s);
+        S->fac_type = S->pool.upload(hg.fac_type, s);
+        S->var_off = S->pool.upload(hg.var_off, s);
+        S->var_edge = S->pool.upload(hg.var_edge, s);
+        if (o.precision == FASTLBP_FP32)
+            upload_params<float>(*S, s, true);
         else
-            upload_params<double>(g.get(), false);
-        g->d.phi = (Belief *)g->dev(sizeof(Belief) * std::max(hg.V, 1));
-        g->d.bel = (Belief *)g->dev(sizeof(Belief) * std::max(hg.V, 1));
-        g->d.msg = g->dev(g->msg_bytes() * std::max<int64_t>(hg.E, 1));
-        g->d.state = (RunState *)g->dev(sizeof(RunState));
-        g->d.marg = (double *)g->dev(sizeof(double) * std::max(hg.V, 1));
-        HIPCHK(hipMemsetAsync(g->d.msg, 0, g->msg_bytes() * std::max<int64_t>(hg.E, 1), g->stream));
-        HIPCHK(hipMemsetAsync(g->d.bel, 0, sizeof(Belief) * std::max(hg.V, 1), g->stream));
-        HIPCHK(hipMemsetAsync(g->d.state, 0, sizeof(RunState), g->stream));
-        upload_phi(g.get());
-        set_schedule(g.get(), FASTLBP_SCHED_FLOODING, nullptr);
+            upload_params<double>(*S, s, false);
+        g->S = S;
+        g->P = make_plan(*S, g->alloc, s, FASTLBP_SCHED_FLOODING, nullptr);
+        g->evidence.assign(hg.V, -1);
+        HIPCHK(hipHostMalloc((void **)&g->h_state, sizeof(RunState), hipHostMallocDefault));
+        alloc_state(g.get());
     } catch (OomError &) {
         set_error("device allocation failed");
         return FASTLBP_E_OOM;
@@ -669,6 +902,32 @@ int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *f
     } catch (std::bad_alloc &) {
         set_error("host allocation failed");
         return FASTLBP_E_OOM;
+    }
+    *out = g.release();
+    return FASTLBP_OK;
+}
+
+int fastlbp_graph_clone(fastlbp_graph_t src, fastlbp_graph_t *out) {
+    clear_error();
+    if (!src || !out) {
+        set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    std::unique_ptr<fastlbp_graph> g(new fastlbp_graph());
+    g->opts = src->opts;
+    g->opts.stream = nullptr;  // every handle gets its own stream
+    g->alloc = src->alloc;
+    g->S = src->S;
+    g->P = src->P;
+    g->evidence.assign(src->hg().V, -1);
+    try {
+        finish_handle(g.get());
+    } catch (OomError &) {
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
+    } catch (DeviceError &e) {
+        return device_error(e);
     }
     *out = g.release();
     return FASTLBP_OK;
@@ -686,37 +945,33 @@ int fastlbp_schedule_set(fastlbp_graph_t g, int32_t kind, const int32_t *edge_ra
         set_error("unknown schedule kind");
         return FASTLBP_E_INVALID_ARG;
     }
-    if (kind == FASTLBP_SCHED_RANKED && !edge_rank && g->hg.E > 0) {
+    if (kind == FASTLBP_SCHED_RANKED && !edge_rank && g->hg().E > 0) {
         set_error("RANKED needs edge_rank");
         return FASTLBP_E_BAD_SCHEDULE;
     }
-    HostPlan keep = g->plan;
-    int keep_kind = g->sched_kind;
     try {
-        set_schedule(g, kind, edge_rank);
+        HIPCHK(hipSetDevice(g->opts.device));
+        HIPCHK(hipStreamSynchronize(g->L.stream));
+        auto P = make_plan(*g->S, g->alloc, g->L.stream, kind, edge_rank);
+        g->drop_graph();
+        g->P = P;  // other handles sharing the old plan keep it
     } catch (OomError &) {
-        g->plan = keep;
-        g->sched_kind = keep_kind;
-        try {
-            upload_plan(g);
-        } catch (...) {
-        }
         set_error("device allocation failed");
         return FASTLBP_E_OOM;
     } catch (DeviceError &e) {
         return device_error(e);
     }
-    if (num_levels_out) *num_levels_out = g->plan.num_levels;
+    if (num_levels_out) *num_levels_out = g->P->hp.num_levels;
     return FASTLBP_OK;
 }
 
 int fastlbp_schedule_levels(fastlbp_graph_t g, int32_t *level_of_edge) {
     clear_error();
-    if (!g || (!level_of_edge && g->hg.E > 0)) {
+    if (!g || (!level_of_edge && g->hg().E > 0)) {
         set_error("invalid argument");
         return FASTLBP_E_INVALID_ARG;
     }
-    if (g->hg.E) std::memcpy(level_of_edge, g->plan.level_of_edge.data(), sizeof(int32_t) * g->hg.E);
+    if (g->hg().E) std::memcpy(level_of_edge, g->P->hp.level_of_edge.data(), sizeof(int32_t) * g->hg().E);
     return FASTLBP_OK;
 }
 
@@ -726,18 +981,11 @@ int fastlbp_evidence_set(fastlbp_graph_t g, int32_t n, const int32_t *vars, cons
         set_error("invalid argument");
         return FASTLBP_E_INVALID_ARG;
     }
-    for (int32_t i = 0; i < n; ++i)
-        if (vars[i] < 0 || vars[i] >= g->hg.V || values[i] < -1 || values[i] > 1) {
-            set_error("evidence entry " + std::to_string(i) + " out of range");
-            return FASTLBP_E_INVALID_ARG;
-        }
-    for (int32_t i = 0; i < n; ++i) g->hg.evidence[vars[i]] = values[i];
     try {
-        upload_phi(g);
+        return set_evidence(g, n, vars, values);
     } catch (DeviceError &e) {
         return device_error(e);
     }
-    return FASTLBP_OK;
 }
 
 int fastlbp_evidence_clear(fastlbp_graph_t g) {
@@ -746,11 +994,19 @@ int fastlbp_evidence_clear(fastlbp_graph_t g) {
         set_error("graph is NULL");
         return FASTLBP_E_INVALID_ARG;
     }
-    std::fill(g->hg.evidence.begin(), g->hg.evidence.end(), int8_t(-1));
+    std::fill(g->evidence.begin(), g->evidence.end(), int8_t(-1));
     try {
         upload_phi(g);
     } catch (DeviceError &e) {
         return device_error(e);
+    }
+    return FASTLBP_OK;
+}
+
+static int check_run_args(int32_t max_iters, double tol, double damping) {
+    if (max_iters < 0 || !(tol >= 0.0) || !(damping >= 0.0 && damping < 1.0)) {
+        set_error("need max_iters >= 0, tol >= 0, 0 <= damping < 1");
+        return FASTLBP_E_INVALID_ARG;
     }
     return FASTLBP_OK;
 }
@@ -761,35 +1017,86 @@ int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping
         set_error("graph is NULL");
         return FASTLBP_E_INVALID_ARG;
     }
-    if (max_iters < 0 || !(tol >= 0.0) || !(damping >= 0.0 && damping < 1.0)) {
-        set_error("need max_iters >= 0, tol >= 0, 0 <= damping < 1");
-        return FASTLBP_E_INVALID_ARG;
-    }
+    int rc = check_run_args(max_iters, tol, damping);
+    if (rc) return rc;
     int exec = choose_executor(g);
     try {
         HIPCHK(hipSetDevice(g->opts.device));
-        HIPCHK(hipEventRecord(g->ev0, g->stream));
-        if (g->precision == FASTLBP_FP32)
+        hipStream_t s = g->L.stream;
+        HIPCHK(hipEventRecord(g->L.ev0, s));
+        if (g->precision() == FASTLBP_FP32)
             run_dispatch<PolLog32>(g, max_iters, tol, damping, exec);
         else
             run_dispatch<PolLin64>(g, max_iters, tol, damping, exec);
-        HIPCHK(hipEventRecord(g->ev1, g->stream));
-        HIPCHK(hipMemcpyAsync(g->h_state, g->d.state, sizeof(RunState), hipMemcpyDeviceToHost, g->stream));
-        HIPCHK(hipStreamSynchronize(g->stream));
+        HIPCHK(hipEventRecord(g->L.ev1, s));
+        HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-        fastlbp_run_stats s{};
-        s.iterations = g->h_state->iter;
-        s.converged = g->h_state->converged;
-        s.residual = g->h_state->last_r;
-        s.contradictions = (int64_t)g->h_state->contra;
-        s.levels = g->plan.num_levels;
-        s.executor = exec;
-        s.algorithmic_bytes_per_iter = g->plan.bytes_per_iter;
-        s.device_ms = ms;
-        s.message_updates = g->plan.updates_per_iter * int64_t(s.iterations);
-        g->last = s;
-        if (stats) *stats = s;
+        HIPCHK(hipEventElapsedTime(&ms, g->L.ev0, g->L.ev1));
+        fastlbp_run_stats st;
+        fill_stats(g, exec, ms, st);
+        if (stats) *stats = st;
+    } catch (OomError &) {
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
+    } catch (DeviceError &e) {
+        return device_error(e);
+    }
+    return FASTLBP_OK;
+}
+
+int fastlbp_run_batch(int32_t n, fastlbp_graph_t *graphs, int32_t max_iters, double tol, double damping,
+                      fastlbp_run_stats *stats) {
+    clear_error();
+    if (n < 0 || (n > 0 && !graphs)) {
+        set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (n == 0) return FASTLBP_OK;
+    int rc = check_run_args(max_iters, tol, damping);
+    if (rc) return rc;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!graphs[i]) {
+            set_error("graph is NULL");
+            return FASTLBP_E_INVALID_ARG;
+        }
+        if (graphs[i]->precision() != graphs[0]->precision() || graphs[i]->opts.device != graphs[0]->opts.device) {
+            set_error("a batch needs one precision and one device");
+            return FASTLBP_E_INVALID_ARG;
+        }
+        for (int32_t j = 0; j < i; ++j)
+            if (graphs[j] == graphs[i]) {
+                set_error("a handle appears twice in the batch");
+                return FASTLBP_E_INVALID_ARG;
+            }
+    }
+    fastlbp_graph *g0 = graphs[0];
+    try {
+        HIPCHK(hipSetDevice(g0->opts.device));
+        for (int32_t i = 0; i < n; ++i) HIPCHK(hipStreamSynchronize(graphs[i]->L.stream));
+        hipStream_t s = g0->L.stream;
+        for (int32_t i = 0; i < n; ++i) k_run_init_step<<<1, 64, 0, s>>>(graphs[i]->st, max_iters, tol, max_iters);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(g0->L.ev0, s));
+        std::vector<double> damps(n, damping);
+        if (g0->precision() == FASTLBP_FP32)
+            launch_persistent<PolLog32>(g0->L, n, graphs, damps.data());
+        else
+            launch_persistent<PolLin64>(g0->L, n, graphs, damps.data());
+        HIPCHK(hipEventRecord(g0->L.ev1, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g0->L.ev0, g0->L.ev1));
+        for (int32_t i = 0; i < n; ++i) {
+            HIPCHK(hipMemcpyAsync(graphs[i]->h_state, graphs[i]->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            fastlbp_run_stats st;
+            fill_stats(graphs[i], FASTLBP_EXEC_PERSISTENT, ms, st);
+            if (stats) stats[i] = st;
+        }
+    } catch (OomError &) {
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
     } catch (DeviceError &e) {
         return device_error(e);
     }
@@ -798,21 +1105,13 @@ int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping
 
 int fastlbp_marginals(fastlbp_graph_t g, double *p1) {
     clear_error();
-    if (!g || (!p1 && g->hg.V > 0)) {
+    if (!g || (!p1 && g->hg().V > 0)) {
         set_error("invalid argument");
         return FASTLBP_E_INVALID_ARG;
     }
-    if (g->hg.V == 0) return FASTLBP_OK;
     try {
         HIPCHK(hipSetDevice(g->opts.device));
-        if (g->precision == FASTLBP_FP32)
-            launch_init_beliefs<PolLog32>(g, g->view<PolLog32>(0.0));
-        else
-            launch_init_beliefs<PolLin64>(g, g->view<PolLin64>(0.0));
-        k_marginals<<<grid_for(g->hg.V, 256), 256, 0, g->stream>>>(g->d.bel, g->hg.V, g->d.marg);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(p1, g->d.marg, sizeof(double) * g->hg.V, hipMemcpyDeviceToHost, g->stream));
-        HIPCHK(hipStreamSynchronize(g->stream));
+        marginals_into(g, p1);
     } catch (DeviceError &e) {
         return device_error(e);
     }
@@ -821,26 +1120,28 @@ int fastlbp_marginals(fastlbp_graph_t g, double *p1) {
 
 int fastlbp_messages_get(fastlbp_graph_t g, double *f2v_p1) {
     clear_error();
-    if (!g || (!f2v_p1 && g->hg.E > 0)) {
+    if (!g || (!f2v_p1 && g->hg().E > 0)) {
         set_error("invalid argument");
         return FASTLBP_E_INVALID_ARG;
     }
-    int64_t E = g->hg.E;
+    const HostGraph &hg = g->hg();
+    int64_t E = hg.E;
     if (!E) return FASTLBP_OK;
     try {
         std::vector<double> l(E);
-        if (g->precision == FASTLBP_FP32) {
+        hipStream_t s = g->L.stream;
+        if (g->precision() == FASTLBP_FP32) {
             std::vector<float> f(E);
-            HIPCHK(hipMemcpyAsync(f.data(), g->d.msg, 4 * E, hipMemcpyDeviceToHost, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
+            HIPCHK(hipMemcpyAsync(f.data(), g->msg, 4 * E, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
             for (int64_t e = 0; e < E; ++e) l[e] = f[e];
         } else {
-            HIPCHK(hipMemcpyAsync(l.data(), g->d.msg, 8 * E, hipMemcpyDeviceToHost, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
+            HIPCHK(hipMemcpyAsync(l.data(), g->msg, 8 * E, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
         }
         for (int64_t e = 0; e < E; ++e) {
-            if (g->hg.fac_type[g->hg.edge_fac[e]] == FASTLBP_PRIOR)
-                f2v_p1[e] = g->hg.fac_param[g->hg.edge_fac[e]];
+            if (hg.fac_type[hg.edge_fac[e]] == FASTLBP_PRIOR)
+                f2v_p1[e] = hg.fac_param[hg.edge_fac[e]];
             else
                 f2v_p1[e] = 1.0 / (1.0 + std::exp2(-l[e]));
         }
@@ -852,11 +1153,12 @@ int fastlbp_messages_get(fastlbp_graph_t g, double *f2v_p1) {
 
 int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1) {
     clear_error();
-    if (!g || (!f2v_p1 && g->hg.E > 0)) {
+    if (!g || (!f2v_p1 && g->hg().E > 0)) {
         set_error("invalid argument");
         return FASTLBP_E_INVALID_ARG;
     }
-    int64_t E = g->hg.E;
+    const HostGraph &hg = g->hg();
+    int64_t E = hg.E;
     for (int64_t e = 0; e < E; ++e)
         if (!(f2v_p1[e] >= 0.0 && f2v_p1[e] <= 1.0)) {
             set_error("message " + std::to_string(e) + " outside [0,1]");
@@ -866,17 +1168,18 @@ int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1) {
     try {
         std::vector<double> l(E, 0.0);
         for (int64_t e = 0; e < E; ++e) {
-            if (g->hg.fac_type[g->hg.edge_fac[e]] == FASTLBP_PRIOR) continue;
+            if (hg.fac_type[hg.edge_fac[e]] == FASTLBP_PRIOR) continue;
             double p = f2v_p1[e];
             l[e] = (p >= 1.0) ? INFINITY : (p <= 0.0 ? -INFINITY : std::log2(p) - std::log2(1.0 - p));
         }
-        if (g->precision == FASTLBP_FP32) {
+        hipStream_t s = g->L.stream;
+        if (g->precision() == FASTLBP_FP32) {
             std::vector<float> f(l.begin(), l.end());
-            HIPCHK(hipMemcpyAsync(g->d.msg, f.data(), 4 * E, hipMemcpyHostToDevice, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
+            HIPCHK(hipMemcpyAsync(g->msg, f.data(), 4 * E, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
         } else {
-            HIPCHK(hipMemcpyAsync(g->d.msg, l.data(), 8 * E, hipMemcpyHostToDevice, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
+            HIPCHK(hipMemcpyAsync(g->msg, l.data(), 8 * E, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
         }
     } catch (DeviceError &e) {
         return device_error(e);
@@ -891,8 +1194,8 @@ int fastlbp_messages_reset(fastlbp_graph_t g) {
         return FASTLBP_E_INVALID_ARG;
     }
     try {
-        HIPCHK(hipMemsetAsync(g->d.msg, 0, g->msg_bytes() * std::max<int64_t>(g->hg.E, 1), g->stream));
-        HIPCHK(hipStreamSynchronize(g->stream));
+        HIPCHK(hipMemsetAsync(g->msg, 0, g->S->msg_bytes() * std::max<int64_t>(g->hg().E, 1), g->L.stream));
+        HIPCHK(hipStreamSynchronize(g->L.stream));
     } catch (DeviceError &e) {
         return device_error(e);
     }

@@ -1,0 +1,352 @@
+// Continuous-batching query server (the interactive feedback loop of Section 5.2.2 at scale).
+//
+// A request is a graph handle plus evidence clamps and run parameters. One host thread runs the
+// loop: admit waiting requests while the number of active runs stays within max_active and the
+// resident state of the active graphs within the memory budget (a graph with a request in flight
+// is not admitted twice: its messages are one state), advance every active run by step_iters
+// iterations in one persistent launch (one workgroup per run, so the runs overlap on the device),
+// then retire the runs that finished and copy their marginals out. Requests that arrive while a
+// step runs join at the next step. Messages stay resident in the handle, so a re-query after new
+// evidence starts warm.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fastlbp.h"
+#include "internal.h"
+
+using namespace fastlbp;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    fastlbp_graph *g = nullptr;
+    std::vector<int32_t> ev_vars;
+    std::vector<int8_t> ev_vals;
+    int32_t max_iters = 0;
+    double tol = 0.0, damping = 0.0;
+    Clock::time_point t_submit, t_start, t_done;
+    int status = 1;  // 1 pending, 0 done, < 0 failed with that code
+    std::string error;
+    std::vector<double> p1;
+    fastlbp_run_stats stats{};
+    bool warm = false;
+};
+
+}  // namespace
+
+struct fastlbp_server {
+    fastlbp_server_options opts{};
+    Launcher *launcher = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> pending;
+    std::vector<std::shared_ptr<Request>> active;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
+    std::unordered_map<fastlbp_graph *, int> runs_of_graph;  // completed runs per handle (warm starts)
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread th;
+    size_t resident = 0;
+    // statistics
+    std::vector<double> lat_ms;
+    int64_t completed = 0, updates = 0, steps = 0;
+    double busy_ms = 0.0;
+    Clock::time_point t0 = Clock::now();
+
+    void loop();
+};
+
+void fastlbp_server::loop() {
+    (void)hipSetDevice(opts.device);
+    std::vector<fastlbp_graph *> gs;
+    std::vector<double> damp;
+    while (true) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
+            if (stop && active.empty()) break;
+            // admission: FIFO, skipping requests whose graph is busy; stop at the first request
+            // that does not fit the memory budget
+            for (auto it = pending.begin(); it != pending.end() && int(active.size()) < opts.max_active;) {
+                auto r = *it;
+                bool busy = false;
+                for (auto &a : active) busy = busy || a->g == r->g;
+                if (busy) {
+                    ++it;
+                    continue;
+                }
+                size_t need = graph_state_bytes(r->g);
+                if (!active.empty() && resident + need > opts.memory_budget) break;
+                it = pending.erase(it);
+                try {
+                    int rc = set_evidence(r->g, int32_t(r->ev_vars.size()), r->ev_vars.data(), r->ev_vals.data());
+                    if (rc) {
+                        r->status = rc;
+                        r->error = fastlbp_last_error();
+                        cv_done.notify_all();
+                        continue;
+                    }
+                    step_begin(r->g, r->max_iters, r->tol, 0);
+                } catch (DeviceError &e) {
+                    r->status = FASTLBP_E_DEVICE;
+                    r->error = e.msg;
+                    cv_done.notify_all();
+                    continue;
+                }
+                r->warm = runs_of_graph[r->g] > 0;
+                r->t_start = Clock::now();
+                resident += need;
+                active.push_back(r);
+            }
+            gs.clear();
+            damp.clear();
+            for (auto &a : active) {
+                gs.push_back(a->g);
+                damp.push_back(a->damping);
+            }
+        }
+        if (gs.empty()) continue;
+        // one step: every active run advances by up to step_iters iterations
+        auto ts = Clock::now();
+        std::vector<std::shared_ptr<Request>> finished;
+        std::string err;
+        try {
+            step_run(*launcher, int(gs.size()), gs.data(), damp.data(), opts.step_iters);
+            for (size_t i = 0; i < gs.size(); ++i) read_state(gs[i], launcher_stream(launcher));
+        } catch (DeviceError &e) {
+            err = e.msg;
+        }
+        double step_ms = std::chrono::duration<double, std::milli>(Clock::now() - ts).count();
+        std::unique_lock<std::mutex> lk(mu);
+        ++steps;
+        busy_ms += step_ms;
+        for (auto it = active.begin(); it != active.end();) {
+            auto r = *it;
+            const RunState &hs = graph_host_state(r->g);
+            if (err.empty() && !hs.done) {
+                ++it;
+                continue;
+            }
+            if (!err.empty()) {
+                r->status = FASTLBP_E_DEVICE;
+                r->error = err;
+            } else {
+                try {
+                    r->p1.resize(graph_num_vars(r->g));
+                    marginals_into(r->g, r->p1.data());
+                    fill_stats_public(r->g, r->stats, 0.f);
+                    r->status = 0;
+                } catch (DeviceError &e) {
+                    r->status = FASTLBP_E_DEVICE;
+                    r->error = e.msg;
+                }
+            }
+            r->t_done = Clock::now();
+            resident -= graph_state_bytes(r->g);
+            runs_of_graph[r->g] += 1;
+            if (r->status == 0) {
+                lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+                ++completed;
+                updates += r->stats.message_updates;
+            }
+            it = active.erase(it);
+        }
+        cv_done.notify_all();
+    }
+}
+
+extern "C" {
+
+void fastlbp_server_options_default(fastlbp_server_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->precision = FASTLBP_FP32;
+    o->max_active = 256;
+    o->step_iters = 2;
+    o->memory_budget = 0;
+}
+
+int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *out) {
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    fastlbp_server_options o;
+    fastlbp_server_options_default(&o);
+    if (opts) o = *opts;
+    if (o.max_active < 1 || o.step_iters < 1 || (o.precision != FASTLBP_FP32 && o.precision != FASTLBP_FP64)) {
+        set_error("need max_active >= 1, step_iters >= 1 and a valid precision");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    std::unique_ptr<fastlbp_server> s(new fastlbp_server());
+    try {
+        if (hipSetDevice(o.device) != hipSuccess) throw DeviceError{"hipSetDevice failed"};
+        if (o.memory_budget == 0) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) throw DeviceError{"hipMemGetInfo failed"};
+            o.memory_budget = free_b / 10 * 8;
+        }
+        s->opts = o;
+        s->launcher = launcher_create(o.device, nullptr, Alloc{});
+    } catch (DeviceError &e) {
+        (void)hipGetLastError();
+        set_error(e.msg);
+        return FASTLBP_E_DEVICE;
+    } catch (OomError &) {
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
+    }
+    s->th = std::thread([srv = s.get()] { srv->loop(); });
+    *out = s.release();
+    return FASTLBP_OK;
+}
+
+int fastlbp_server_submit(fastlbp_server_t s, fastlbp_graph_t g, int32_t n_ev, const int32_t *ev_vars,
+                          const int8_t *ev_vals, int32_t max_iters, double tol, double damping, uint64_t *ticket) {
+    clear_error();
+    if (!s || !g || !ticket || n_ev < 0 || (n_ev > 0 && (!ev_vars || !ev_vals))) {
+        set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (max_iters < 0 || !(tol >= 0.0) || !(damping >= 0.0 && damping < 1.0)) {
+        set_error("need max_iters >= 0, tol >= 0, 0 <= damping < 1");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (graph_device(g) != s->opts.device || graph_precision(g) != s->opts.precision) {
+        set_error("graph device or precision differs from the server's");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (graph_state_bytes(g) > s->opts.memory_budget) {
+        set_error("graph state exceeds the server's memory budget");
+        return FASTLBP_E_TOO_LARGE;
+    }
+    auto r = std::make_shared<Request>();
+    r->g = g;
+    r->ev_vars.assign(ev_vars, ev_vars + n_ev);
+    r->ev_vals.assign(ev_vals, ev_vals + n_ev);
+    r->max_iters = max_iters;
+    r->tol = tol;
+    r->damping = damping;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            set_error("server is shutting down");
+            return FASTLBP_E_STATE;
+        }
+        r->ticket = s->next_ticket++;
+        s->by_ticket[r->ticket] = r;
+        s->pending.push_back(r);
+    }
+    s->cv_work.notify_one();
+    *ticket = r->ticket;
+    return FASTLBP_OK;
+}
+
+static int collect(fastlbp_server_t s, std::shared_ptr<Request> r, double *p1, fastlbp_run_stats *st,
+                   double *latency_ms) {
+    s->by_ticket.erase(r->ticket);
+    if (r->status < 0) {
+        set_error(r->error);
+        return r->status;
+    }
+    if (p1 && !r->p1.empty()) std::memcpy(p1, r->p1.data(), sizeof(double) * r->p1.size());
+    if (st) *st = r->stats;
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    return FASTLBP_OK;
+}
+
+int fastlbp_server_poll(fastlbp_server_t s, uint64_t ticket, double *p1, fastlbp_run_stats *st, double *latency_ms) {
+    clear_error();
+    if (!s) {
+        set_error("server is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end()) {
+        set_error("unknown ticket");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (it->second->status == 1) return 1;
+    return collect(s, it->second, p1, st, latency_ms);
+}
+
+int fastlbp_server_wait(fastlbp_server_t s, uint64_t ticket, double *p1, fastlbp_run_stats *st, double *latency_ms) {
+    clear_error();
+    if (!s) {
+        set_error("server is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end()) {
+        set_error("unknown ticket");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    auto r = it->second;
+    s->cv_done.wait(lk, [&] { return r->status != 1; });
+    return collect(s, r, p1, st, latency_ms);
+}
+
+int fastlbp_server_get_stats(fastlbp_server_t s, fastlbp_server_stats *out) {
+    clear_error();
+    if (!s || !out) {
+        set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->completed = s->completed;
+    out->message_updates = s->updates;
+    out->steps = s->steps;
+    out->busy_ms = s->busy_ms;
+    out->pending = int32_t(s->pending.size());
+    out->active = int32_t(s->active.size());
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            size_t k = size_t(q * double(v.size() - 1) + 0.5);
+            return v[std::min(k, v.size() - 1)];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+    }
+    return FASTLBP_OK;
+}
+
+void fastlbp_server_destroy(fastlbp_server_t s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (auto &r : s->pending) {
+            r->status = FASTLBP_E_STATE;
+            r->error = "server destroyed before the request ran";
+        }
+        s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->th.joinable()) s->th.join();
+    s->cv_done.notify_all();
+    launcher_destroy(s->launcher);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""Serving: continuous batching. Requests of different graphs and sizes, including warm re-queries
+after new evidence, are submitted while others run; every result must equal the same request
+sequence run alone on its own handle (within rounding) and match the oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_22337_amd as F
+from paper_2509_22337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-9, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _graphs():
+    # convergent, non-chaotic instances of both generators at a few sizes
+    return [W.smartfl(4, levels=30, width=60, max_iters=100), W.smartfl(11, levels=30, width=60, max_iters=100),
+            W.datalog(1, num_tuples=600, num_rules=450), W.datalog(2, num_tuples=2000, num_rules=1500),
+            W.smartfl(13, levels=30, width=60, max_iters=100)]
+
+
+def _requests(ws, rng):
+    """Two queries per graph: the original clamps, then 1-10 extra clamps (warm re-query)."""
+    reqs = []
+    for gi, w in enumerate(ws):
+        ev = w.evidence
+        reqs.append((gi, np.flatnonzero(ev >= 0).astype(np.int32), ev[ev >= 0].astype(np.int8)))
+    for gi, w in enumerate(ws):
+        k = int(rng.integers(1, 11))
+        if "world" in w.meta:
+            v = rng.choice(w.num_vars, size=k, replace=False).astype(np.int32)
+            x = w.meta["world"][v].astype(np.int8)
+        else:  # datalog: clamp tuples without priors to random values (soft factors only)
+            v = rng.choice(w.meta["num_tuples"], size=k, replace=False).astype(np.int32)
+            x = rng.integers(0, 2, k).astype(np.int8)
+        reqs.append((gi, v, x))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_server_mixed_stream_matches_alone_and_oracle(precision):
+    ws = _graphs()
+    rng = np.random.default_rng(0)
+    reqs = _requests(ws, rng)
+    params = [(w.max_iters, w.tol, w.damping) for w in ws]
+    # alone: each graph's requests in order on its own handle, one at a time
+    alone = []
+    for gi, v, x in reqs:
+        pass
+    solo_h = [F.Graph.from_workload(w, precision=precision, executor="persistent") for w in ws]
+    for h in solo_h:
+        h.evidence_clear()
+    for gi, v, x in reqs:
+        h = solo_h[gi]
+        h.evidence_set(v, x)
+        st = h.run(*params[gi])
+        alone.append((h.marginals(), st))
+    # served: all handles fresh, requests submitted in a staggered stream
+    srv = F.Server(precision=precision, max_active=3, step_iters=3)
+    hs = [F.Graph.from_workload(w, precision=precision) for w in ws]
+    for h in hs:
+        h.evidence_clear()
+    tickets = []
+    for i, (gi, v, x) in enumerate(reqs):
+        tickets.append(srv.submit(hs[gi], v, x, *params[gi]))
+        if i % 3 == 2:
+            time.sleep(0.002)  # later requests arrive while earlier ones run
+    results = [srv.wait(t) for t in tickets]
+    sstats = srv.stats()
+    srv.close()
+    assert sstats["completed"] == len(reqs)
+    # oracle: same evidence sequence, warm start from the oracle's own previous state
+    ev_cur = [np.full(w.num_vars, -1, np.int8) for w in ws]
+    state = [None] * len(ws)
+    for i, (gi, v, x) in enumerate(reqs):
+        w = ws[gi]
+        ev_cur[gi][v] = x
+        m_srv, st_srv, lat = results[i]
+        m_alone, st_alone = alone[i]
+        E = w.num_edges
+        m0, m1 = state[gi] if state[gi] is not None else (np.full(E, 0.5), np.full(E, 0.5))
+        om, om0, om1, ost = oracle.bp_pairs(w, m0, m1, w.max_iters, w.tol, w.damping, ranks=w.edge_rank,
+                                            evidence=ev_cur[gi])
+        state[gi] = (om0, om1)
+        d_alone = np.abs(m_srv - m_alone).max()
+        d_or = np.abs(m_srv - om).max()
+        _say(precision, i, w.name, "iters", st_srv["iterations"], st_alone["iterations"], ost["iterations"],
+             "alone", d_alone, "oracle", d_or, "lat ms %.1f" % lat)
+        assert st_srv["iterations"] == st_alone["iterations"]
+        assert d_alone <= (1e-12 if precision == "fp64" else 1e-6)
+        assert d_or <= TOL[precision]
+    for h in hs + solo_h:
+        h.close()
+
+
+def test_server_errors():
+    w = W.random_tree(2)
+    g = F.Graph.from_workload(w, precision="fp64")
+    srv = F.Server(precision="fp32", max_active=4)
+    with pytest.raises(F.FastLBPError):
+        srv.submit(g)  # precision mismatch
+    with pytest.raises(F.FastLBPError):
+        srv.poll(12345)
+    srv.close()
+    srv = F.Server(precision="fp64", max_active=1, memory_budget=64)
+    with pytest.raises(F.FastLBPError) as ei:
+        srv.submit(g)
+    assert ei.value.code == F.E_TOO_LARGE
+    srv.close()
+    g.close()
