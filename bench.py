@@ -1,15 +1,28 @@
 """Benchmark: factor-to-variable message updates per second and query latency of belief
-propagation on one MI355X, FP32 log-domain messages vs plain FP64.
+propagation on one MI355X, batched FP32 vs plain FP64.
 
-A step is one query: cold-start messages, clamp the query's evidence, run the schedule until the
-residual falls below tol (or max_iters), read back the marginals. The default workload is the
-SmartFL-shaped graph: 200,000 binary variables in 500 layers, one deterministic AND/OR/NOT factor per
-variable over 1-4 predecessors, Beta(9,1) priors, 2% observed variables, forward-backward (TOPO)
-ranked schedule split into levels by the dependency analysis, tol 1e-6, up to 500 iterations.
+Workload: the SmartFL-shaped graph. It has 200,000 binary variables in 500 layers, one
+deterministic AND/OR/NOT factor per variable over 1-4 predecessors (Zipf), Beta(9,1) priors and a
+forward-backward (TOPO) ranked schedule. The dependency analysis splits it into 998 levels. It runs
+with tol 1e-6 and up to 500 iterations.
 
-Prints one JSON line. `value` is FP32 message updates per second over the timed steps; the FP64
-figures, p50/p99 latencies, the roofline of the dominant kernel and the CPU oracle baseline are
-extra fields.
+A query clamps 2% of the variables to a consistent world (a different seeded set per query),
+starts from uniform messages and runs until the residual falls below tol or max_iters is reached.
+It then reads back the marginals. Most evidence sets keep the forward-backward schedule
+oscillating, so those queries run to max_iters.
+
+* step (timed): a batch of --batch queries submitted together to the FP32 continuous-batching
+  server (one workgroup per running query, --step-iters iterations per launch, queries retire as
+  they finish). `value` is the FP32 message updates per second over the timed steps.
+* plain FP64: --fp64-queries of the same queries, one after another, each a single-graph FP64 run.
+* solo FP32: the first query alone (unbatched FP32), for the latency of one query.
+* roofline: the persistent kernel of the batched steps. Its algorithmic bytes (the library's exact
+  per-iteration count times iterations, summed over queries) are divided by the summed kernel time,
+  measured with HIP events on the server's stream.
+* cpu_baseline: the FP64 oracle on one host thread, a bounded number of full iterations of the same
+  graph and schedule.
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -27,47 +40,81 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
-def make_workload(name: str, seed: int):
+def log(*a):
+    print("#", *a, file=sys.stderr, flush=True)
+
+
+def query_evidence(w, q):
+    """Evidence of query q: the workload's own clamps for q = 0, another seeded 2% set otherwise."""
     from paper_2509_22337_amd import workloads as W
-    if name == "smartfl":
-        return W.smartfl(seed), "smartfl_200k_vars_500_levels_fwd_bwd"
-    if name == "datalog":
-        return W.datalog(seed), "datalog_2k_tuples_1500_rules_flooding"
-    if name == "bingo":
-        return W.bingo(seed), "bingo_2M_tuples_4M_rules_flooding"
-    raise SystemExit(f"unknown workload {name}")
+    ev = w.evidence if q == 0 else W.smartfl_evidence(w, seed=1000 + q)
+    v = np.flatnonzero(ev >= 0).astype(np.int32)
+    return v, ev[v].astype(np.int8)
 
 
-def run_queries(F, w, precision, steps, warmup, executor="auto"):
+def batched_steps(F, w, queries, steps, warmup, step_iters):
+    """Continuous-batching FP32 server, all queries of a step submitted at once."""
     import torch
-    g = F.Graph.from_workload(w, precision=precision, executor=executor)
-    lat, dev_ms, updates, iters, bytes_it = [], [], 0, [], 0.0
-    stats = None
-    for i in range(warmup + steps):
-        if i == warmup:
+    base = F.Graph.from_workload(w, precision="fp32", executor="persistent")
+    handles = [base] + [base.clone() for _ in range(len(queries) - 1)]
+    srv = F.Server(precision="fp32", max_active=len(queries), step_iters=step_iters)
+    lat, updates, iters, alg_bytes = [], 0, [], 0.0
+    k0 = None
+    for s in range(warmup + steps):
+        if s == warmup:
             torch.cuda.synchronize()
+            st0 = srv.stats()
             t_start = time.perf_counter()
+        for h in handles:
+            h.messages_reset()
+            h.evidence_clear()
+        tickets = [srv.submit(h, v, x, w.max_iters, w.tol, w.damping) for h, (v, x) in zip(handles, queries)]
+        res = [srv.wait(t) for t in tickets]
+        if s >= warmup:
+            for _, st, l in res:
+                lat.append(l)
+                updates += st["message_updates"]
+                iters.append(st["iterations"])
+                alg_bytes += st["algorithmic_bytes_per_iter"] * st["iterations"]
+        log(f"batched step {s}: {max(r[2] for r in res):.1f} ms, iterations {sorted(r[1]['iterations'] for r in res)[::8]}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    st1 = srv.stats()
+    srv.close()
+    for h in handles:
+        h.close()
+    kernel_ms = st1["kernel_ms"] - st0["kernel_ms"]
+    launches = st1["steps"] - st0["steps"]
+    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, alg_bytes=alg_bytes, kernel_ms=kernel_ms,
+                launches=launches)
+
+
+def sequential_queries(F, w, queries, precision):
+    import torch
+    g = F.Graph.from_workload(w, precision=precision)
+    lat, updates, iters, dev_ms = [], 0, [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for v, x in queries:
         t0 = time.perf_counter()
         g.messages_reset()
-        g.evidence_array(w.evidence)
+        g.evidence_clear()
+        g.evidence_set(v, x)
         st = g.run(w.max_iters, w.tol, w.damping)
-        m = g.marginals()
-        t1 = time.perf_counter()
-        if i >= warmup:
-            lat.append((t1 - t0) * 1e3)
-            dev_ms.append(st["device_ms"])
-            updates += st["message_updates"]
-            iters.append(st["iterations"])
-            stats = st
+        g.marginals()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        updates += st["message_updates"]
+        iters.append(st["iterations"])
+        dev_ms.append(st["device_ms"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     g.close()
-    return dict(wall_s=wall, lat_ms=lat, device_ms=dev_ms, updates=updates, iters=iters, stats=stats, marg=m)
+    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, device_ms=dev_ms)
 
 
 def cpu_baseline(w, budget_s: float):
-    """The oracle (single thread) on a bounded sample: as many full iterations of the same
-    workload and schedule as fit in about `budget_s` seconds (at least one)."""
+    """The oracle (single thread) on a bounded sample: as many full iterations of the same graph,
+    schedule and evidence as fit in about `budget_s` seconds."""
     import oracle
     t0 = time.perf_counter()
     _, _, st = oracle.bp(w, max_iters=1, tol=0.0)
@@ -76,79 +123,100 @@ def cpu_baseline(w, budget_s: float):
     t0 = time.perf_counter()
     _, _, st = oracle.bp(w, max_iters=n, tol=0.0)
     dt = time.perf_counter() - t0
-    return dict(value=st["message_updates"] / dt, unit="message updates/s", cores=1, kind="oracle",
-                sample=f"{n} full iterations of the same graph, schedule and evidence (cold start, tol 0), "
-                       f"{dt:.1f} s, single thread")
+    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle",
+                sample=f"{n} full iterations (cold start, tol 0) of the same 200k-variable graph, forward-backward "
+                       f"schedule and evidence as query 0: {st['message_updates']} updates in {dt:.1f} s")
+
+
+def pct(a, q):
+    return round(float(np.percentile(a, q)), 3)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="smartfl", choices=["smartfl", "datalog", "bingo"])
+    ap.add_argument("--batch", type=int, default=64, help="queries per batched step")
+    ap.add_argument("--step-iters", type=int, default=8, help="iterations per server launch")
+    ap.add_argument("--fp64-queries", type=int, default=3)
+    ap.add_argument("--max-iters", type=int, default=None, help="override the workload's 500")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 leg (profiling)")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
         raise SystemExit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "launches": 5}))
+        return
     import paper_2509_22337_amd as F
+    from paper_2509_22337_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     F.load()
-    w, wname = make_workload(args.workload, args.seed)
-    print(f"# workload {wname}: V={w.num_vars} F={w.num_factors} E={w.num_edges} "
-          f"(non-prior {w.nonprior_edges()})", file=sys.stderr, flush=True)
+    w = W.smartfl(args.seed)
+    if args.max_iters:
+        w.max_iters = args.max_iters
+    queries = [query_evidence(w, q) for q in range(args.batch)]
+    log(f"workload smartfl: V={w.num_vars} F={w.num_factors} E={w.num_edges} (non-prior {w.nonprior_edges()}), "
+        f"{args.batch} queries per step")
 
-    r32 = run_queries(F, w, "fp32", args.steps, args.warmup)
-    print(f"# fp32: {r32['wall_s']*1e3/args.steps:.2f} ms/query, iters {r32['iters']}", file=sys.stderr, flush=True)
-    r64 = None
-    if not args.fp32_only:
-        r64 = run_queries(F, w, "fp64", args.steps, args.warmup)
-        print(f"# fp64: {r64['wall_s']*1e3/args.steps:.2f} ms/query, iters {r64['iters']}", file=sys.stderr,
-              flush=True)
-
-    st = r32["stats"]
-    mups32 = r32["updates"] / r32["wall_s"]
-    # roofline of the dominant kernel (the run's only long kernel): algorithmic bytes of the run's
-    # iterations over the device time of the run, HIP events on the library's stream
-    bytes_run = st["algorithmic_bytes_per_iter"] * st["iterations"]
-    dev_s = float(np.mean(r32["device_ms"])) / 1e3
-    achieved = bytes_run / dev_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "k_persistent" if st["executor"] == F.EXEC_PERSISTENT else "k_fac_thread",
-            "bytes_per_launch": bytes_run, "launch_ms": round(dev_s * 1e3, 3)}
+    rb = batched_steps(F, w, queries, args.steps, args.warmup, args.step_iters)
+    mups_b = rb["updates"] / rb["wall_s"]
+    log(f"batched fp32: {rb['wall_s'] * 1e3 / args.steps:.1f} ms/step, {mups_b / 1e6:.1f} M updates/s")
     out = {
-        "metric": "message updates/sec (f->v), FP32 vs plain FP64; p50/p99 query latency",
-        "value": round(mups32, 1),
+        "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
+        "value": round(mups_b, 1),
         "unit": "message updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r32["wall_s"] * 1e3 / args.steps, 3),
+        "ms_per_step": round(rb["wall_s"] * 1e3 / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wname, "seed": args.seed, "num_vars": w.num_vars, "num_edges": w.num_edges,
-                   "levels": st["levels"], "max_iters": w.max_iters, "tol": w.tol, "damping": w.damping,
-                   "executor": "persistent" if st["executor"] == F.EXEC_PERSISTENT else "levels"},
-        "fp32": {"mups": round(mups32, 1), "p50_ms": round(float(np.percentile(r32["lat_ms"], 50)), 3),
-                 "p99_ms": round(float(np.percentile(r32["lat_ms"], 99)), 3), "iterations": r32["iters"]},
-        "roofline": roof,
+        "config": {"workload": "smartfl_200k_vars_500_layers_fwd_bwd_ranked", "seed": args.seed,
+                   "num_vars": w.num_vars, "num_edges": w.num_edges, "levels": 998, "max_iters": w.max_iters,
+                   "tol": w.tol, "queries_per_step": args.batch, "step_iters": args.step_iters,
+                   "executor": "persistent, one workgroup per query"},
+        "batched_fp32": {"mups": round(mups_b, 1), "p50_ms": pct(rb["lat_ms"], 50), "p99_ms": pct(rb["lat_ms"], 99),
+                         "queries": len(rb["lat_ms"]), "iterations_p50": int(np.median(rb["iters"])),
+                         "iterations_max": int(max(rb["iters"]))},
     }
-    if r64 is not None:
-        out["fp64"] = {"mups": round(r64["updates"] / r64["wall_s"], 1),
-                       "p50_ms": round(float(np.percentile(r64["lat_ms"], 50)), 3),
-                       "p99_ms": round(float(np.percentile(r64["lat_ms"], 99)), 3), "iterations": r64["iters"]}
-        out["fp32_vs_fp64_max_abs_marginal_diff"] = float(np.abs(r32["marg"] - r64["marg"]).max())
+    kernel_s = rb["kernel_ms"] / 1e3
+    achieved = rb["alg_bytes"] / kernel_s / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_persistent<PolLog32>",
+                       "launches": rb["launches"], "avg_launch_ms": round(rb["kernel_ms"] / max(1, rb["launches"]), 4),
+                       "algorithmic_bytes": rb["alg_bytes"]}
+    if not args.batched_only:
+        r64 = sequential_queries(F, w, queries[:args.fp64_queries], "fp64")
+        mups64 = r64["updates"] / r64["wall_s"]
+        log(f"plain fp64: {mups64 / 1e6:.2f} M updates/s, iterations {r64['iters']}")
+        out["plain_fp64"] = {"mups": round(mups64, 1), "p50_ms": pct(r64["lat_ms"], 50),
+                             "p99_ms": pct(r64["lat_ms"], 99), "queries": len(r64["lat_ms"]),
+                             "iterations": r64["iters"]}
+        r32 = sequential_queries(F, w, queries[:1], "fp32")
+        out["solo_fp32"] = {"mups": round(r32["updates"] / r32["wall_s"], 1), "latency_ms": round(r32["lat_ms"][0], 3),
+                            "iterations": r32["iters"][0], "device_ms": round(r32["device_ms"][0], 3)}
+        out["batched_fp32_vs_plain_fp64"] = round(mups_b / mups64, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

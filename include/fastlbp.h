@@ -235,6 +235,8 @@ typedef struct fastlbp_server_stats {
     int64_t message_updates;  /* factor-to-variable updates of the finished requests */
     int64_t steps;            /* steps (persistent launches) so far */
     double busy_ms;           /* wall time spent in steps */
+    double kernel_ms;         /* device time of the steps' persistent kernels (HIP events) */
+    double algorithmic_bytes; /* algorithmic bytes of the finished requests (bytes/iter x iters) */
     double p50_ms, p99_ms;    /* latency (submit to marginals ready) of the finished requests */
     int32_t pending, active;  /* queue length and runs in flight right now */
 } fastlbp_server_stats;

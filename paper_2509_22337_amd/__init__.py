@@ -53,7 +53,8 @@ class ServerOptions(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("message_updates", ctypes.c_int64), ("steps", ctypes.c_int64),
-                ("busy_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("busy_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("algorithmic_bytes", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("pending", ctypes.c_int32), ("active", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
@@ -385,7 +386,7 @@ class Server:
         return t.value
 
     def _collect(self, fn, ticket):
-        p1 = np.zeros(self._nv[ticket])
+        p1 = np.zeros(self._nv.get(ticket, 0))
         st = RunStats()
         lat = ctypes.c_double(0.0)
         rc = fn(self._h, ctypes.c_uint64(ticket), _p(p1), ctypes.byref(st), ctypes.byref(lat))

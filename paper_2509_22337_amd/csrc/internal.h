@@ -52,6 +52,7 @@ void clear_error();
 Launcher *launcher_create(int device, hipStream_t s, const Alloc &a);
 void launcher_destroy(Launcher *l);
 hipStream_t launcher_stream(Launcher *l);
+float launcher_kernel_ms(Launcher *l);  // duration of the last persistent launch (HIP events)
 void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step);
 void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
 void read_state(fastlbp_graph *g, hipStream_t s);

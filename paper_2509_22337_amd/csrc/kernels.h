@@ -205,7 +205,7 @@ __device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename
 }
 
 template <bool ALL_ACTIVE>
-__device__ __forceinline__ bool is_active(const int32_t *edge_level, int32_t e, int level) {
+__device__ __forceinline__ bool is_active(const GPtr<const int32_t> &edge_level, int32_t e, int level) {
     return ALL_ACTIVE || edge_level[e] == level;
 }
 
@@ -218,7 +218,7 @@ __device__ __forceinline__ void factor_not(const DevGraph<typename P::S, typenam
     bool nl[2];
     for (int k = 0; k < 2; ++k) {
         lo[k] = g.msg[b + k];
-        vf[k] = v2f<P>(g.bel[g.edge_var[b + k]], lo[k], nl[k]);
+        vf[k] = v2f<P>(g.bel.ld(g.edge_var[b + k]), lo[k], nl[k]);
     }
     for (int k = 0; k < 2; ++k) {
         if (!is_active<ALL_ACTIVE>(g.edge_level, b + k, level)) continue;
@@ -348,12 +348,12 @@ __device__ __forceinline__ HF<typename P::V> load_leaf(const DevGraph<typename P
                                                        int32_t e, typename P::S &old, bool &null) {
     using V = typename P::V;
     old = g.msg[e];
-    typename P::S vf = v2f<P>(g.bel[g.edge_var[e]], old, null);
+    typename P::S vf = v2f<P>(g.bel.ld(g.edge_var[e]), old, null);
     if (null) return identity<P>();
     V m0, m1;
     P::leaf(vf, m0, m1);
     Pair<V> ep = {P::zero(), P::one()};
-    if (type == T_NOISY_OR) ep = g.epar[e];
+    if (type == T_NOISY_OR) ep = g.epar.ld(e);
     return make_leaf<P>(type, m0, m1, ep);
 }
 
@@ -377,12 +377,12 @@ __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typena
         return;
     }
     const int32_t n = d - 1;
-    const Pair<V> fp = g.fpar[a];
+    const Pair<V> fp = g.fpar.ld(a);
     // head (last edge): its v->f message weights the messages to the inputs
     const int32_t eh = b + n;
     S lh_old = g.msg[eh];
     bool null_h;
-    S vfh = v2f<P>(g.bel[g.edge_var[eh]], lh_old, null_h);
+    S vfh = v2f<P>(g.bel.ld(g.edge_var[eh]), lh_old, null_h);
     V my0 = P::zero(), my1 = P::zero();
     if (!null_h) P::leaf(vfh, my0, my1);
     // chunk of inputs owned by this lane
@@ -478,7 +478,7 @@ __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typena
                 if (is_active<ALL_ACTIVE>(g.edge_level, e, level)) {
                     HF<V> xo = combine<P>(run, sx[j]);
                     Pair<V> ep = {P::zero(), P::one()};
-                    if (type == T_NOISY_OR) ep = g.epar[e];
+                    if (type == T_NOISY_OR) ep = g.epar.ld(e);
                     V o0, o1;
                     input_msg<P>(type, xo, my0, my1, fp, ep, o0, o1);
                     int others_null = ntot - (nl ? 1 : 0) + (null_h ? 1 : 0);
@@ -505,9 +505,9 @@ __device__ __forceinline__ void belief_add(Belief &B, typename P::S l) {
 
 template <class P>
 __device__ __forceinline__ void var_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t v) {
-    Belief B = g.phi[v];
+    Belief B = g.phi.ld(v);
     for (int32_t q = g.var_off[v]; q < g.var_off[v + 1]; ++q) belief_add<P>(B, g.msg[g.var_edge[q]]);
-    g.bel[v] = B;
+    g.bel.st(v, B);
 }
 
 // One wavefront per variable (high degree); fixed-shape reduction, so the result is deterministic.
@@ -522,11 +522,11 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
         B.nneg += __shfl_xor(B.nneg, k, 64);
     }
     if (lane == 0) {
-        Belief p = g.phi[v];
+        Belief p = g.phi.ld(v);
         p.fin += B.fin;
         p.npos += B.npos;
         p.nneg += B.nneg;
-        g.bel[v] = p;
+        g.bel.st(v, p);
     }
 }
 
@@ -537,17 +537,6 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
 // thread issues all of a task's dynamic loads (messages, beliefs) at once.
 // ------------------------------------------------------------------------------------------------
 
-struct FacRec {
-    int4 r0;  // b, meta = d | type << 8 | active << 16, factor id, u0
-    int4 r1;  // u1 .. u4
-    int4 r2;  // u5 .. u7, unused
-};
-
-struct VarRec {
-    int4 r0;  // v, row start, degree, e0
-    int4 r1;  // e1 .. e4
-};
-
 // One factor of degree d <= 8 from values in registers: lo[k] the old message of edge b + k,
 // vf[k] its variable-to-factor message, nl[k] whether that is the null message. Bit k of `active`
 // selects the edges the level writes.
@@ -555,7 +544,7 @@ template <class P, bool DAMP>
 __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int d,
                                              int32_t b, unsigned active, const Pair<typename P::V> &fp,
                                              const typename P::S (&lo)[8], const typename P::S (&vf)[8],
-                                             const bool (&nl)[8], Acc &acc) {
+                                             const bool (&nl)[8], const Pair<typename P::V> (&ep)[8], Acc &acc) {
     using S = typename P::S;
     using V = typename P::V;
     if (type == T_NOT) {
@@ -590,9 +579,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
             if (!nl[k]) {
                 V m0, m1;
                 P::leaf(vf[k], m0, m1);
-                Pair<V> ep = {P::zero(), P::one()};
-                if (type == T_NOISY_OR) ep = g.epar[b + k];
-                lf[k] = make_leaf<P>(type, m0, m1, ep);
+                lf[k] = make_leaf<P>(type, m0, m1, ep[k]);
             } else {
                 ++nnull;
             }
@@ -623,10 +610,8 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
         if (k < n) {
             if ((active >> k) & 1u) {
                 HF<V> xo = combine<P>(run, sx[k]);
-                Pair<V> ep = {P::zero(), P::one()};
-                if (type == T_NOISY_OR) ep = g.epar[b + k];
                 V o0, o1;
-                input_msg<P>(type, xo, my0, my1, fp, ep, o0, o1);
+                input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
                 int others_null = nnull - (nl[k] ? 1 : 0) + (nlh ? 1 : 0);
                 g.msg[b + k] = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
             }
@@ -635,41 +620,79 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
     }
 }
 
+// Loads of one factor of degree <= 8 (edge range b, d) whose variables u[] are known, all issued
+// before any is used: slots past the degree re-read slot 0 and are ignored.
 template <class P, bool DAMP>
-__device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc) {
+__device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
+                                                     int d, int type, int32_t fac, unsigned active,
+                                                     const int32_t (&u)[8], Acc &acc) {
     using S = typename P::S;
     using V = typename P::V;
-    const int32_t b = r.r0.x;
-    const int d = r.r0.y & 0xff, type = (r.r0.y >> 8) & 0xff;
-    const unsigned active = (unsigned)(r.r0.y >> 16) & 0xffu;
-    const int32_t u[8] = {r.r0.w, r.r1.x, r.r1.y, r.r1.z, r.r1.w, r.r2.x, r.r2.y, r.r2.z};
-    S lo[8], vf[8];
-    bool nl[8];
+    S lo[8];
+    Belief B[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        lo[k] = (S)0;
-        vf[k] = (S)0;
-        nl[k] = false;
-        if (k < d) {
-            lo[k] = g.msg[b + k];
-            vf[k] = v2f<P>(g.bel[u[k]], lo[k], nl[k]);
-        }
+        const int kk = k < d ? k : 0;
+        lo[k] = g.msg[b + kk];
+        B[k] = g.bel.ld(u[kk]);
+    }
+    Pair<V> ep[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ep[k] = {P::zero(), P::one()};
+    if (type == T_NOISY_OR) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ep[k] = g.epar.ld(b + (k < d ? k : 0));
     }
     Pair<V> fp = {P::zero(), P::one()};
-    if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar[r.r0.z];
-    factor_local<P, DAMP>(g, type, d, b, active, fp, lo, vf, nl, acc);
+    if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar.ld(fac);
+    S vf[8];
+    bool nl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) vf[k] = v2f<P>(B[k], lo[k], nl[k]);
+    factor_local<P, DAMP>(g, type, d, b, active, fp, lo, vf, nl, ep, acc);
+}
+
+template <class P, bool DAMP>
+__device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc) {
+    const int d = r.meta & 0xff, type = (r.meta >> 8) & 0xff;
+    const unsigned active = (unsigned)(r.meta >> 16) & 0xffu;
+    const int32_t u[8] = {r.u[0], r.u[1], r.u[2], r.u[3], r.u[4], r.u[5], r.u[6], r.u[7]};
+    factor_fetch_compute<P, DAMP>(g, r.b, d, type, r.fac, active, u, acc);
+}
+
+// A factor of degree <= 8 from the factor list (wide executor): structure loads, then the same
+// fetch-then-compute as the records.
+template <class P, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int level,
+                                              Acc &acc) {
+    const int32_t b = g.fac_off[a];
+    const int d = g.fac_off[a + 1] - b;
+    const int type = g.fac_type[a];
+    int32_t u[8];
+    unsigned active = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int kk = k < d ? k : 0;
+        u[k] = g.edge_var[b + kk];
+        bool on = ALL_ACTIVE || g.edge_level[b + kk] == level;
+        active |= (on && k < d) ? (1u << k) : 0u;
+    }
+    factor_fetch_compute<P, DAMP>(g, b, d, type, a, active, u, acc);
 }
 
 template <class P>
 __device__ __forceinline__ void var_rec(const DevGraph<typename P::S, typename P::V> &g, const VarRec &r) {
-    const int32_t v = r.r0.x, start = r.r0.y, cnt = r.r0.z;
-    const int32_t e[kVarRecEdges] = {r.r0.w, r.r1.x, r.r1.y, r.r1.z, r.r1.w};
-    Belief B = g.phi[v];
+    using S = typename P::S;
+    const int32_t cnt = r.cnt;
+    Belief B = g.phi.ld(r.v);
+    S m[kVarRecEdges];
+#pragma unroll
+    for (int j = 0; j < kVarRecEdges; ++j) m[j] = g.msg[r.e[j < cnt ? j : 0]];
 #pragma unroll
     for (int j = 0; j < kVarRecEdges; ++j)
-        if (j < cnt) belief_add<P>(B, g.msg[e[j]]);
-    for (int32_t j = kVarRecEdges; j < cnt; ++j) belief_add<P>(B, g.msg[g.var_edge[start + j]]);
-    g.bel[v] = B;
+        if (j < cnt) belief_add<P>(B, m[j]);
+    for (int32_t j = kVarRecEdges; j < cnt; ++j) belief_add<P>(B, g.msg[g.var_edge[r.start + j]]);
+    g.bel.st(r.v, B);
 }
 
 }  // namespace fastlbp

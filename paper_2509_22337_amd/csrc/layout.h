@@ -9,9 +9,47 @@
 // factors are folded into phi_v together with evidence, so they never occupy message slots on the
 // device.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
+#include <type_traits>
 
 namespace fastlbp {
+
+// Pointer to global memory. Indexing goes through an address_space(1) pointer, so device code
+// uses global (not flat) memory instructions even when the pointer itself was loaded from memory
+// (as in the per-workgroup run descriptors of the persistent executor).
+template <class T>
+struct GPtr {
+    typedef __attribute__((address_space(1))) T gT;
+    typedef __attribute__((address_space(1))) int gint;
+    T *p;
+    __host__ __device__ GPtr() : p(nullptr) {}
+    __host__ __device__ GPtr(T *q) : p(q) {}
+    // scalar element access
+    __device__ __forceinline__ gT &operator[](int64_t i) const { return ((gT *)p)[i]; }
+    __device__ __forceinline__ gT *operator->() const { return (gT *)p; }
+    // whole-struct load and store, moved as dwords
+    __device__ __forceinline__ typename std::remove_const<T>::type ld(int64_t i) const {
+        static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+        const gint *q = (const gint *)(p + i);
+        int tmp[sizeof(T) / 4];
+#pragma unroll
+        for (int k = 0; k < int(sizeof(T) / 4); ++k) tmp[k] = q[k];
+        typename std::remove_const<T>::type out;
+        __builtin_memcpy(&out, tmp, sizeof(T));
+        return out;
+    }
+    __device__ __forceinline__ void st(int64_t i, const T &v) const {
+        static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+        int tmp[sizeof(T) / 4];
+        __builtin_memcpy(tmp, &v, sizeof(T));
+        gint *q = (gint *)(p + i);
+#pragma unroll
+        for (int k = 0; k < int(sizeof(T) / 4); ++k) q[k] = tmp[k];
+    }
+    __host__ __device__ T *get() const { return p; }
+};
 
 // Finite part plus counts of infinite terms of a sum of LLRs. A sum with both +inf and -inf
 // terms is the product of two exactly-zero entries: the "null" message (0, 0).
@@ -47,7 +85,7 @@ constexpr int kThreadMaxDeg = 8;     // one thread per factor
 constexpr int kWaveMaxDeg = 1025;    // one wavefront per factor: 64 lanes x 16 inputs + head
 constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 1024 x 16 + head
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
-constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record
+constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record (VarRec::e)
 
 enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_COUNT = 3 };
 enum { VB_THREAD = 0, VB_WAVE = 1, VB_COUNT = 2 };
@@ -56,17 +94,17 @@ template <typename S, typename V>
 struct DevGraph {
     int32_t num_vars;
     int32_t num_edges;
-    const int32_t *fac_off;    // [F+1]
-    const int32_t *edge_var;   // [E]
-    const uint8_t *fac_type;   // [F]
-    const Pair<V> *fpar;       // [F]
-    const Pair<V> *epar;       // [E]
-    const int32_t *var_off;    // [V+1] over non-PRIOR edges
-    const int32_t *var_edge;   // [E_np] edge ids, variable-major
-    const Belief *phi;         // [V] priors + evidence
-    Belief *bel;               // [V]
-    S *msg;                    // [E]
-    const int32_t *edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
+    GPtr<const int32_t> fac_off;    // [F+1]
+    GPtr<const int32_t> edge_var;   // [E]
+    GPtr<const uint8_t> fac_type;   // [F]
+    GPtr<const Pair<V>> fpar;       // [F]
+    GPtr<const Pair<V>> epar;       // [E]
+    GPtr<const int32_t> var_off;    // [V+1] over non-PRIOR edges
+    GPtr<const int32_t> var_edge;   // [E_np] edge ids, variable-major
+    GPtr<const Belief> phi;         // [V] priors + evidence
+    GPtr<Belief> bel;               // [V]
+    GPtr<S> msg;                    // [E]
+    GPtr<const int32_t> edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
     V damp_old;                // lambda in the value domain
     V damp_new;                // 1 - lambda in the value domain
 };
@@ -74,20 +112,33 @@ struct DevGraph {
 // Work lists of one schedule, concatenated over the executed levels. Level L owns
 // fac_list[b][fac_lvl_off[b][L] .. fac_lvl_off[b][L+1]) for every factor bucket b, and the same for
 // variables. init_var lists every variable (all levels' beliefs are rebuilt from it at run start).
+// Task records of the persistent executor: everything static about a task resolved on the host.
+struct alignas(16) FacRec {
+    int32_t b;     // first edge
+    int32_t meta;  // degree | type << 8 | (edges the level writes, bit k = edge b + k) << 16
+    int32_t fac;   // factor id (for its parameters)
+    int32_t u[9];  // variable of edge b + k, k < degree (<= 8)
+};
+
+struct alignas(16) VarRec {
+    int32_t v, start, cnt;  // variable, first position in var_edge, degree
+    int32_t e[5];           // its first edges (the rest from var_edge)
+};
+
 struct DevPlan {
     int32_t num_levels;
     int32_t all_active;  // 1: every listed factor writes all of its edges (flooding)
-    const int32_t *fac_list[FB_COUNT];
-    const int32_t *fac_lvl_off[FB_COUNT];  // [num_levels+1]
-    const int32_t *var_list[VB_COUNT];
-    const int32_t *var_lvl_off[VB_COUNT];  // [num_levels+1]
-    const int32_t *init_var[VB_COUNT];
+    GPtr<const int32_t> fac_list[FB_COUNT];
+    GPtr<const int32_t> fac_lvl_off[FB_COUNT];  // [num_levels+1]
+    GPtr<const int32_t> var_list[VB_COUNT];
+    GPtr<const int32_t> var_lvl_off[VB_COUNT];  // [num_levels+1]
+    GPtr<const int32_t> init_var[VB_COUNT];
     int32_t init_var_count[VB_COUNT];
     // per-level task records of the thread buckets (persistent executor)
-    const void *frec;            // FacRec per factor task of the thread bucket
-    const int32_t *frec_off;     // [num_levels+1]
-    const void *vrec;            // VarRec per variable task of the thread bucket
-    const int32_t *vrec_off;     // [num_levels+1]
+    GPtr<const FacRec> frec;
+    GPtr<const int32_t> frec_off;  // [num_levels+1]
+    GPtr<const VarRec> vrec;
+    GPtr<const int32_t> vrec_off;  // [num_levels+1]
 };
 
 }  // namespace fastlbp

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_fac_thread(DevGraph<typename P::S, type
     if (st->done) return;
     Acc acc = {0.0, 0u};
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-        factor_team<P, 1, kThreadMaxDeg - 1, ALL, DAMP>(g, list[i], 0, level, acc, nullptr);
+        factor_thread<P, ALL, DAMP>(g, list[i], level, acc);
     flush_acc(acc, st);
 }
 
@@ -145,7 +145,7 @@ template <class P>
 struct RunDesc {
     DevGraph<typename P::S, typename P::V> g;
     DevPlan plan;
-    RunState *st;
+    GPtr<RunState> st;
 };
 
 // One workgroup of NT threads runs every level and iteration of one run, with workgroup barriers
@@ -166,16 +166,16 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
     const RunDesc<P> &D = descs[blockIdx.x];
     const DevGraph<typename P::S, typename P::V> g = D.g;
     const DevPlan plan = D.plan;
-    RunState *st = D.st;
+    GPtr<RunState> st = D.st;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const FacRec *frec = (const FacRec *)plan.frec;
-    const VarRec *vrec = (const VarRec *)plan.vrec;
+    const GPtr<const FacRec> frec = plan.frec;
+    const GPtr<const VarRec> vrec = plan.vrec;
     const int32_t NL = plan.num_levels;
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
     if (tid == 0) s_done = st->done || st->iter >= st->step_end;
     FacRec fr = {};
-    if (NL > 0 && plan.frec_off[0] + tid < plan.frec_off[1]) fr = frec[plan.frec_off[0] + tid];
+    if (NL > 0 && plan.frec_off[0] + tid < plan.frec_off[1]) fr = frec.ld(plan.frec_off[0] + tid);
     __syncthreads();
     while (!s_done) {
         Acc acc = {0.0, 0u};
@@ -183,17 +183,17 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
             const int32_t f0 = plan.frec_off[L], f1 = plan.frec_off[L + 1];
             const int32_t v0 = plan.vrec_off[L], v1 = plan.vrec_off[L + 1];
             VarRec vr = {};
-            if (v0 + tid < v1) vr = vrec[v0 + tid];  // used by this level's variable phase
+            if (v0 + tid < v1) vr = vrec.ld(v0 + tid);  // used by this level's variable phase
             if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc);
-            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec[i], acc);
+            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld(i), acc);
             if (TEAMS) {
-                const int32_t *lst = plan.fac_list[FB_WAVE];
+                const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
                 int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
                 for (int32_t i = o0 + w; i < o1; i += NW)
                     factor_team<P, 64, 16, false, DAMP>(g, lst[i], lane, L, acc, nullptr);
             }
             if (TEAMS) {
-                const int32_t *lst = plan.fac_list[FB_BLOCK];
+                const GPtr<const int32_t> lst = plan.fac_list[FB_BLOCK];
                 int32_t o0 = plan.fac_lvl_off[FB_BLOCK][L], o1 = plan.fac_lvl_off[FB_BLOCK][L + 1];
                 for (int32_t i = o0; i < o1; ++i)
                     factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, &lds);
@@ -204,12 +204,12 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
                 const int32_t Ln = (L + 1 < NL) ? L + 1 : 0;
                 const int32_t n0 = plan.frec_off[Ln], n1 = plan.frec_off[Ln + 1];
                 fr = FacRec{};
-                if (n0 + tid < n1) fr = frec[n0 + tid];
+                if (n0 + tid < n1) fr = frec.ld(n0 + tid);
             }
             if (v0 + tid < v1) var_rec<P>(g, vr);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec[i]);
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld(i));
             {
-                const int32_t *lst = plan.var_list[VB_WAVE];
+                const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
                 int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
                 for (int32_t i = o0 + w; i < o1; i += NW) var_wave<P>(g, lst[i], lane);
             }
@@ -326,9 +326,9 @@ struct Plan {
             p.init_var[b] = init_var[b];
             p.init_var_count[b] = int32_t(hp.init_var[b].size());
         }
-        p.frec = frec;
+        p.frec = (const FacRec *)frec;
         p.frec_off = fac_lvl_off[FB_THREAD];
-        p.vrec = vrec;
+        p.vrec = (const VarRec *)vrec;
         p.vrec_off = var_lvl_off[VB_THREAD];
         return p;
     }
@@ -343,6 +343,8 @@ struct Launcher {
     size_t desc_cap = 0;
     std::vector<unsigned char> hdesc;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t k0 = nullptr, k1 = nullptr;  // around the last persistent kernel
+    float last_kernel_ms = 0.f;
     void init(hipStream_t s, const Alloc &a) {
         pool.alloc = a;
         if (s) {
@@ -353,6 +355,8 @@ struct Launcher {
         }
         HIPCHK(hipEventCreate(&ev0));
         HIPCHK(hipEventCreate(&ev1));
+        HIPCHK(hipEventCreate(&k0));
+        HIPCHK(hipEventCreate(&k1));
     }
     void *descs(size_t bytes) {
         if (bytes > desc_cap) {
@@ -367,6 +371,8 @@ struct Launcher {
         pool.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (k0) (void)hipEventDestroy(k0);
+        if (k1) (void)hipEventDestroy(k1);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -566,13 +572,13 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
     k_finalize<<<1, 64, 0, s>>>(g->st);
 }
 
-// Workgroup size of the persistent executor: 1024 threads for float32, 512 for float64 (whose
-// factor code needs more than the 128 registers a 1024-thread workgroup allows).
-// FASTLBP_PERSISTENT_THREADS=512|1024 overrides.
-static int persistent_threads(int precision) {
+// Workgroup size of the persistent executor: 1024 threads for float32 plans without wavefront or
+// workgroup factors, else 512 (float64 factor code and the team paths need more than the 128
+// registers a 1024-thread workgroup allows). FASTLBP_PERSISTENT_THREADS=512|1024 overrides.
+static int persistent_threads(int precision, bool teams) {
     const char *e = std::getenv("FASTLBP_PERSISTENT_THREADS");
     if (e && (std::atoi(e) == 512 || std::atoi(e) == 1024)) return std::atoi(e);
-    return precision == FASTLBP_FP32 ? 1024 : 512;
+    return (precision == FASTLBP_FP32 && !teams) ? 1024 : 512;
 }
 
 static int choose_executor(const fastlbp_graph *g) {
@@ -639,12 +645,13 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     for (int i = 0; i < n; ++i) {
         h[i].g = gs[i]->view<PP>(damping[i]);
         h[i].plan = gs[i]->P->view();
-        h[i].st = gs[i]->st;
+        h[i].st = GPtr<RunState>(gs[i]->st);
     }
     HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, lc.stream));
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
-    int nt = persistent_threads(gs[0]->precision());
+    int nt = persistent_threads(gs[0]->precision(), teams);
     hipStream_t s = lc.stream;
+    HIPCHK(hipEventRecord(lc.k0, s));
 #define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, 0, s>>>(dd)
     if (nt == 1024) {
         if (damp && teams) FASTLBP_LAUNCH(true, true, 1024);
@@ -659,8 +666,10 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     }
 #undef FASTLBP_LAUNCH
     HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(lc.k1, s));
     // the host staging buffer may be rewritten by the next call
     HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipEventElapsedTime(&lc.last_kernel_ms, lc.k0, lc.k1));
 }
 
 __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int32_t step) {
@@ -776,6 +785,7 @@ Launcher *launcher_create(int device, hipStream_t s, const Alloc &a) {
 }
 void launcher_destroy(Launcher *l) { delete l; }
 hipStream_t launcher_stream(Launcher *l) { return l->stream; }
+float launcher_kernel_ms(Launcher *l) { return l->last_kernel_ms; }
 int graph_device(fastlbp_graph *g) { return g->opts.device; }
 int graph_precision(fastlbp_graph *g) { return g->precision(); }
 size_t graph_state_bytes(fastlbp_graph *g) { return g->state_bytes(); }

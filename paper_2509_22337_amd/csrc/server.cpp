@@ -62,7 +62,7 @@ struct fastlbp_server {
     // statistics
     std::vector<double> lat_ms;
     int64_t completed = 0, updates = 0, steps = 0;
-    double busy_ms = 0.0;
+    double busy_ms = 0.0, kernel_ms = 0.0, alg_bytes = 0.0;
     Clock::time_point t0 = Clock::now();
 
     void loop();
@@ -132,6 +132,7 @@ void fastlbp_server::loop() {
         std::unique_lock<std::mutex> lk(mu);
         ++steps;
         busy_ms += step_ms;
+        if (err.empty()) kernel_ms += launcher_kernel_ms(launcher);
         for (auto it = active.begin(); it != active.end();) {
             auto r = *it;
             const RunState &hs = graph_host_state(r->g);
@@ -160,6 +161,7 @@ void fastlbp_server::loop() {
                 lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
                 ++completed;
                 updates += r->stats.message_updates;
+                alg_bytes += r->stats.algorithmic_bytes_per_iter * double(r->stats.iterations);
             }
             it = active.erase(it);
         }
@@ -316,6 +318,8 @@ int fastlbp_server_get_stats(fastlbp_server_t s, fastlbp_server_stats *out) {
     out->message_updates = s->updates;
     out->steps = s->steps;
     out->busy_ms = s->busy_ms;
+    out->kernel_ms = s->kernel_ms;
+    out->algorithmic_bytes = s->alg_bytes;
     out->pending = int32_t(s->pending.size());
     out->active = int32_t(s->active.size());
     if (!s->lat_ms.empty()) {
