@@ -113,7 +113,9 @@ typedef struct fastlbp_run_stats {
     int64_t contradictions;      /* messages replaced by uniform during the run */
     int32_t levels;              /* levels per iteration (dependency analysis) */
     int32_t executor;            /* FASTLBP_EXEC_LEVELS or FASTLBP_EXEC_PERSISTENT */
-    double algorithmic_bytes_per_iter; /* bytes an iteration must move at minimum (see design notes) */
+    double algorithmic_bytes_per_iter; /* bytes one iteration must move at minimum: for every executed
+                                    * factor and variable task its structure, parameters, beliefs
+                                    * and messages read once, and every written message stored once */
     double device_ms;            /* device time of the run, HIP events on the handle's stream */
     int64_t message_updates;     /* factor-to-variable updates performed (edges x iterations) */
 } fastlbp_run_stats;
@@ -233,9 +235,10 @@ typedef struct fastlbp_server_options {
 typedef struct fastlbp_server_stats {
     int64_t completed;        /* requests finished successfully */
     int64_t message_updates;  /* factor-to-variable updates of the finished requests */
-    int64_t steps;            /* steps (persistent launches) so far */
+    int64_t steps;            /* steps so far */
     double busy_ms;           /* wall time spent in steps */
-    double kernel_ms;         /* device time of the steps' persistent kernels (HIP events) */
+    double kernel_ms;         /* device time of the steps (HIP events): per step, the longest of
+                               * its persistent launch and the wide runs on their own streams */
     double algorithmic_bytes; /* algorithmic bytes of the finished requests (bytes/iter x iters) */
     double p50_ms, p99_ms;    /* latency (submit to marginals ready) of the finished requests */
     int32_t pending, active;  /* queue length and runs in flight right now */
@@ -249,8 +252,11 @@ int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *
 
 /* Queues a request: apply the n_ev clamps (values 0/1, -1 releases) to the graph's evidence, then
  * run max_iters iterations at most (tol, damping as in fastlbp_run) from the graph's current
- * messages (warm start). The handle belongs to the server until the request completes: the
- * caller must not use it meanwhile. Requests on one handle run one after another, in order.
+ * messages (warm start). A run whose graph the AUTO rule assigns to the LEVELS executor (levels
+ * too wide for one workgroup) is stepped with that executor on the handle's own stream, alongside
+ * the persistent launch of the other runs. The handle belongs to the server until the request
+ * completes: the caller must not use it meanwhile. Requests on one handle run one after another,
+ * in order.
  * *ticket identifies the request. Errors: E_INVALID_ARG (device or precision mismatch),
  * E_TOO_LARGE (graph state above the memory budget), E_STATE (server shutting down). */
 int fastlbp_server_submit(fastlbp_server_t s, fastlbp_graph_t g, int32_t n_ev, const int32_t *ev_vars,

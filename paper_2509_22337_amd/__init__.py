@@ -382,11 +382,13 @@ class Server:
         t = ctypes.c_uint64(0)
         _check(load().fastlbp_server_submit(self._h, graph._h, len(v), _p(v), _p(x), int(max_iters), float(tol),
                                             float(damping), ctypes.byref(t)))
-        self._nv[t.value] = graph.num_vars
+        self._nv[t.value] = np.empty(graph.num_vars)  # receives the marginals
         return t.value
 
     def _collect(self, fn, ticket):
-        p1 = np.zeros(self._nv.get(ticket, 0))
+        p1 = self._nv.get(ticket)
+        if p1 is None:
+            p1 = np.empty(0)
         st = RunStats()
         lat = ctypes.c_double(0.0)
         rc = fn(self._h, ctypes.c_uint64(ticket), _p(p1), ctypes.byref(st), ctypes.byref(lat))

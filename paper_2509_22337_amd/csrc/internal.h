@@ -56,6 +56,12 @@ float launcher_kernel_ms(Launcher *l);  // duration of the last persistent launc
 void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step);
 void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
 void read_state(fastlbp_graph *g, hipStream_t s);
+// Runs whose levels are too wide for one workgroup (the LEVELS executor) are stepped on their own
+// stream instead: step_levels_enqueue queues `iters` iterations without waiting, step_levels_finish
+// waits for them and returns their device time in ms.
+bool graph_wide(fastlbp_graph *g);
+void step_levels_enqueue(fastlbp_graph *g, double damping, int32_t iters);
+float step_levels_finish(fastlbp_graph *g);
 const RunState &graph_host_state(fastlbp_graph *g);
 void marginals_into(fastlbp_graph *g, double *p1);
 void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms);

@@ -55,6 +55,31 @@ struct PolLog32 {
         return contra ? 0.0f : v1 - v0;
     }
     static __device__ __forceinline__ S from_double(double x) { return (float)x; }
+    // |P(x=1) under a - P(x=1) under b| for the residual, in float32. With hi >= lo and
+    // s(x) = 1 / (1 + 2^-x), s(hi) - s(lo) = s(lo) s(-hi) (2^(hi-lo) - 1): three factors, each to
+    // a few ulp, so the difference keeps a relative error of about 1e-6 instead of the absolute
+    // 1e-7 of subtracting two rounded probabilities (which would blur a tol of 1e-6).
+    static __device__ __forceinline__ double delta_p1(S a, S b) {
+        const float hi = fmaxf(a, b), lo = fminf(a, b);
+        const float d = hi - lo;
+        if (!(d > 0.0f)) return 0.0;
+        if (d < 32.0f) {  // both finite here
+            const float sl = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-lo));
+            const float sh = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(hi));
+            float em;
+            if (d < 0.25f) {  // 2^d - 1 by its series in x = d ln 2 (x < 0.18, truncation < 3e-7 relative)
+                const float x = d * 0.69314718f;
+                em = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f)))));
+            } else {
+                em = __builtin_amdgcn_exp2f(d) - 1.0f;
+            }
+            return (double)(sl * sh * em);
+        }
+        // far apart (or infinite): no cancellation to fear
+        const float ph = hi == INFINITY ? 1.0f : __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-hi));
+        const float pl = lo == -INFINITY ? 0.0f : __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-lo));
+        return (double)(ph - pl);
+    }
 };
 
 // float64, linear domain.
@@ -81,6 +106,9 @@ struct PolLin64 {
         return contra ? 0.0 : log2(v1) - log2(v0);
     }
     static __device__ __forceinline__ S from_double(double x) { return x; }
+    static __device__ __forceinline__ double delta_p1(S a, S b) {
+        return fabs(1.0 / (1.0 + exp2(-a)) - 1.0 / (1.0 + exp2(-b)));
+    }
 };
 
 // P(x = 1) of an LLR in bits, in float64 (used for the residual).
@@ -184,7 +212,7 @@ __device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S
         l = (S)0;
     }
     if (contra) acc.contra++;
-    if (DAMP) {
+    if (DAMP && g.damped) {
         V a0, a1, b0, b1;
         P::leaf(old, a0, a1);
         P::leaf(l, b0, b1);
@@ -192,8 +220,7 @@ __device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S
         l = P::llr(P::add(P::mul(g.damp_old, a0), P::mul(g.damp_new, b0)),
                    P::add(P::mul(g.damp_old, a1), P::mul(g.damp_new, b1)), c2);
     }
-    double d = fabs(prob1((double)l) - prob1((double)old));
-    acc.r = fmax(acc.r, d);
+    acc.r = fmax(acc.r, P::delta_p1(l, old));
     return l;
 }
 

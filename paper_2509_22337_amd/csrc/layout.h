@@ -40,6 +40,17 @@ struct GPtr {
         __builtin_memcpy(&out, tmp, sizeof(T));
         return out;
     }
+    // the same, streaming past the caches (data read once per iteration)
+    __device__ __forceinline__ typename std::remove_const<T>::type ld_stream(int64_t i) const {
+        static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+        const gint *q = (const gint *)(p + i);
+        int tmp[sizeof(T) / 4];
+#pragma unroll
+        for (int k = 0; k < int(sizeof(T) / 4); ++k) tmp[k] = __builtin_nontemporal_load(q + k);
+        typename std::remove_const<T>::type out;
+        __builtin_memcpy(&out, tmp, sizeof(T));
+        return out;
+    }
     __device__ __forceinline__ void st(int64_t i, const T &v) const {
         static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
         int tmp[sizeof(T) / 4];
@@ -107,6 +118,7 @@ struct DevGraph {
     GPtr<const int32_t> edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
     V damp_old;                // lambda in the value domain
     V damp_new;                // 1 - lambda in the value domain
+    int32_t damped;            // lambda > 0 (a damped kernel leaves undamped runs' messages as computed)
 };
 
 // Work lists of one schedule, concatenated over the executed levels. Level L owns

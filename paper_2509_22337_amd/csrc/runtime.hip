@@ -156,13 +156,14 @@ struct RunDesc {
 // (plans with factors of degree > 8). A launch returns when the run is done or its iteration
 // count reaches st->step_end, so a caller can advance many runs in steps.
 template <class P, bool DAMP, bool TEAMS, int NT>
-__global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
+__global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int32_t lds_levels) {
     using V = typename P::V;
     constexpr int NW = NT / 64;
     __shared__ TeamLds<V> lds;
     __shared__ double red_r[NW];
     __shared__ unsigned int red_c[NW];
     __shared__ int s_done;
+    extern __shared__ int32_t s_off[];  // factor then variable record offsets, when they fit
     const RunDesc<P> &D = descs[blockIdx.x];
     const DevGraph<typename P::S, typename P::V> g = D.g;
     const DevPlan plan = D.plan;
@@ -171,21 +172,31 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
     const GPtr<const FacRec> frec = plan.frec;
     const GPtr<const VarRec> vrec = plan.vrec;
     const int32_t NL = plan.num_levels;
+    // per-level record offsets: staged once in LDS so that a level does not start with a round
+    // trip to memory (schedules deeper than the launch's LDS allowance read them from memory)
+    const bool off_lds = NL <= lds_levels;
+    if (off_lds)
+        for (int32_t i = tid; i <= NL; i += NT) {
+            s_off[i] = plan.frec_off[i];
+            s_off[lds_levels + 1 + i] = plan.vrec_off[i];
+        }
+    auto foff = [&](int32_t L) { return off_lds ? s_off[L] : (int32_t)plan.frec_off[L]; };
+    auto voff = [&](int32_t L) { return off_lds ? s_off[lds_levels + 1 + L] : (int32_t)plan.vrec_off[L]; };
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
     if (tid == 0) s_done = st->done || st->iter >= st->step_end;
-    FacRec fr = {};
-    if (NL > 0 && plan.frec_off[0] + tid < plan.frec_off[1]) fr = frec.ld(plan.frec_off[0] + tid);
     __syncthreads();
+    FacRec fr = {};
+    if (NL > 0 && foff(0) + tid < foff(1)) fr = frec.ld_stream(foff(0) + tid);
     while (!s_done) {
         Acc acc = {0.0, 0u};
         for (int32_t L = 0; L < NL; ++L) {
-            const int32_t f0 = plan.frec_off[L], f1 = plan.frec_off[L + 1];
-            const int32_t v0 = plan.vrec_off[L], v1 = plan.vrec_off[L + 1];
+            const int32_t f0 = foff(L), f1 = foff(L + 1);
+            const int32_t v0 = voff(L), v1 = voff(L + 1);
             VarRec vr = {};
-            if (v0 + tid < v1) vr = vrec.ld(v0 + tid);  // used by this level's variable phase
+            if (v0 + tid < v1) vr = vrec.ld_stream(v0 + tid);  // used by this level's variable phase
             if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc);
-            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld(i), acc);
+            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc);
             if (TEAMS) {
                 const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
                 int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
@@ -202,12 +213,12 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs) {
             {
                 // factor records of the next level (level 0 of the next iteration after the last)
                 const int32_t Ln = (L + 1 < NL) ? L + 1 : 0;
-                const int32_t n0 = plan.frec_off[Ln], n1 = plan.frec_off[Ln + 1];
+                const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
                 fr = FacRec{};
-                if (n0 + tid < n1) fr = frec.ld(n0 + tid);
+                if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
             }
             if (v0 + tid < v1) var_rec<P>(g, vr);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld(i));
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
             {
                 const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
                 int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
@@ -436,6 +447,7 @@ struct fastlbp_graph {
         g.bel = bel;
         g.msg = (typename PP::S *)msg;
         g.edge_level = P->edge_level;
+        g.damped = damping > 0.0 ? 1 : 0;
         if (precision() == FASTLBP_FP32) {
             g.damp_old = (typename PP::V)(damping > 0 ? std::log2(damping) : -INFINITY);
             g.damp_new = (typename PP::V)std::log2(1.0 - damping);
@@ -589,6 +601,22 @@ static int choose_executor(const fastlbp_graph *g) {
     return FASTLBP_EXEC_LEVELS;
 }
 
+// The handle's hipGraph of K captured iterations, re-captured when K, damping or the plan changed.
+template <class PP, bool ALL, bool DAMP>
+static void ensure_iteration_graph(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, int K,
+                                   double damping) {
+    if (g->gexec && g->graph_iters == K && g->graph_damping == damping && g->graph_plan == g->P.get()) return;
+    g->drop_graph();
+    hipStream_t s = g->L.stream;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+    HIPCHK(hipStreamEndCapture(s, &g->graph));
+    HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
+    g->graph_iters = K;
+    g->graph_damping = damping;
+    g->graph_plan = g->P.get();
+}
+
 template <class PP, bool ALL, bool DAMP>
 static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping) {
     auto dg = g->view<PP>(damping);
@@ -603,16 +631,7 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
     int K = std::max(1, std::min(32, 2048 / per_iter_kernels));
     K = std::min(K, max_iters);
     bool use_graph = g->opts.use_graph != 0;
-    if (use_graph && (!g->gexec || g->graph_iters != K || g->graph_damping != damping || g->graph_plan != g->P.get())) {
-        g->drop_graph();
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
-        HIPCHK(hipStreamEndCapture(s, &g->graph));
-        HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
-        g->graph_iters = K;
-        g->graph_damping = damping;
-        g->graph_plan = g->P.get();
-    }
+    if (use_graph) ensure_iteration_graph<PP, ALL, DAMP>(g, dg, K, damping);
     int done_iters = 0;
     while (true) {
         if (use_graph)
@@ -651,8 +670,13 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
     int nt = persistent_threads(gs[0]->precision(), teams);
     hipStream_t s = lc.stream;
+    // LDS for the record offsets of the deepest schedule in the launch, up to 8192 levels (64 KiB)
+    int32_t max_levels = 0;
+    for (int i = 0; i < n; ++i) max_levels = std::max(max_levels, gs[i]->P->hp.exec_levels);
+    const int32_t lds_levels = std::min<int32_t>(max_levels, 8191);
+    const size_t lds_bytes = sizeof(int32_t) * 2 * size_t(lds_levels + 1);
     HIPCHK(hipEventRecord(lc.k0, s));
-#define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, 0, s>>>(dd)
+#define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, lds_bytes, s>>>(dd, lds_levels)
     if (nt == 1024) {
         if (damp && teams) FASTLBP_LAUNCH(true, true, 1024);
         else if (damp) FASTLBP_LAUNCH(true, false, 1024);
@@ -747,6 +771,50 @@ void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *dampi
         launch_persistent<PolLin64>(lc, n, gs, damping);
 }
 
+// A server step of a run on the LEVELS executor: beliefs rebuilt (the evidence may be new), then
+// `iters` iterations on the handle's own stream, so the step overlaps the persistent launch of the
+// narrow runs. Iterations after the run is done return at once.
+template <class PP, bool ALL, bool DAMP>
+static void step_levels_t(fastlbp_graph *g, double damping, int32_t iters) {
+    auto dg = g->view<PP>(damping);
+    hipStream_t s = g->L.stream;
+    HIPCHK(hipEventRecord(g->L.k0, s));
+    launch_init_beliefs<PP>(g, dg);
+    if (g->opts.use_graph) {
+        ensure_iteration_graph<PP, ALL, DAMP>(g, dg, iters, damping);
+        HIPCHK(hipGraphLaunch(g->gexec, s));
+    } else {
+        for (int k = 0; k < iters; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(g->L.k1, s));
+}
+
+template <class PP>
+static void step_levels_p(fastlbp_graph *g, double damping, int32_t iters) {
+    bool all = g->P->hp.all_active != 0, damp = damping > 0.0;
+    if (all && damp) step_levels_t<PP, true, true>(g, damping, iters);
+    if (all && !damp) step_levels_t<PP, true, false>(g, damping, iters);
+    if (!all && damp) step_levels_t<PP, false, true>(g, damping, iters);
+    if (!all && !damp) step_levels_t<PP, false, false>(g, damping, iters);
+}
+
+bool graph_wide(fastlbp_graph *g) { return choose_executor(g) == FASTLBP_EXEC_LEVELS; }
+
+void step_levels_enqueue(fastlbp_graph *g, double damping, int32_t iters) {
+    if (g->precision() == FASTLBP_FP32)
+        step_levels_p<PolLog32>(g, damping, iters);
+    else
+        step_levels_p<PolLin64>(g, damping, iters);
+}
+
+float step_levels_finish(fastlbp_graph *g) {
+    HIPCHK(hipStreamSynchronize(g->L.stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, g->L.k0, g->L.k1));
+    return ms;
+}
+
 void read_state(fastlbp_graph *g, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -764,7 +832,7 @@ void marginals_into(fastlbp_graph *g, double *p1) {
     HIPCHK(hipStreamSynchronize(g->L.stream));
 }
 
-void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms) { fill_stats(g, FASTLBP_EXEC_PERSISTENT, ms, s); }
+void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms) { fill_stats(g, choose_executor(g), ms, s); }
 
 int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t *values) {
     for (int32_t i = 0; i < n; ++i)

@@ -4,8 +4,9 @@
 // loop: admit waiting requests while the number of active runs stays within max_active and the
 // resident state of the active graphs within the memory budget (a graph with a request in flight
 // is not admitted twice: its messages are one state), advance every active run by step_iters
-// iterations in one persistent launch (one workgroup per run, so the runs overlap on the device),
-// then retire the runs that finished and copy their marginals out. Requests that arrive while a
+// iterations in one persistent launch (one workgroup per run, so the runs overlap on the device;
+// runs whose levels are too wide for one workgroup take the LEVELS executor on their own stream,
+// concurrently with that launch), then retire the runs that finished and copy their marginals out. Requests that arrive while a
 // step runs join at the next step. Messages stay resident in the handle, so a re-query after new
 // evidence starts warm.
 #include <hip/hip_runtime_api.h>
@@ -70,8 +71,8 @@ struct fastlbp_server {
 
 void fastlbp_server::loop() {
     (void)hipSetDevice(opts.device);
-    std::vector<fastlbp_graph *> gs;
-    std::vector<double> damp;
+    std::vector<fastlbp_graph *> gs, narrow, wide;
+    std::vector<double> damp, narrow_damp;
     while (true) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -122,17 +123,42 @@ void fastlbp_server::loop() {
         auto ts = Clock::now();
         std::vector<std::shared_ptr<Request>> finished;
         std::string err;
+        float dev_ms = 0.f;
         try {
-            step_run(*launcher, int(gs.size()), gs.data(), damp.data(), opts.step_iters);
+            // wide runs first (asynchronous, each on its own stream), then the persistent launch of
+            // the narrow runs, which overlaps them
+            narrow.clear();
+            wide.clear();
+            narrow_damp.clear();
+            for (size_t i = 0; i < gs.size(); ++i) {
+                if (graph_wide(gs[i])) {
+                    wide.push_back(gs[i]);
+                    step_levels_enqueue(gs[i], damp[i], opts.step_iters);
+                } else {
+                    narrow.push_back(gs[i]);
+                    narrow_damp.push_back(damp[i]);
+                }
+            }
+            if (!narrow.empty()) {
+                step_run(*launcher, int(narrow.size()), narrow.data(), narrow_damp.data(), opts.step_iters);
+                dev_ms = launcher_kernel_ms(launcher);
+            }
+            for (auto *g : wide) dev_ms = std::max(dev_ms, step_levels_finish(g));
             for (size_t i = 0; i < gs.size(); ++i) read_state(gs[i], launcher_stream(launcher));
         } catch (DeviceError &e) {
             err = e.msg;
+            for (auto *g : wide) {
+                try {
+                    graph_sync(g);
+                } catch (DeviceError &) {
+                }
+            }
         }
         double step_ms = std::chrono::duration<double, std::milli>(Clock::now() - ts).count();
         std::unique_lock<std::mutex> lk(mu);
         ++steps;
         busy_ms += step_ms;
-        if (err.empty()) kernel_ms += launcher_kernel_ms(launcher);
+        if (err.empty()) kernel_ms += dev_ms;
         for (auto it = active.begin(); it != active.end();) {
             auto r = *it;
             const RunState &hs = graph_host_state(r->g);

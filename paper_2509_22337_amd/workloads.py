@@ -435,6 +435,105 @@ def bingo(seed: int = 0, num_tuples: int = 2_000_000, num_rules: int = 4_000_000
     return w
 
 
+def datalog_scaled(seed: int, num_vars: int, body=(2, 3), rule_p=(0.8, 0.99), prior_frac: float = 0.05,
+                   prior_p=(0.1, 0.9), max_iters: int = 50, tol: float = 0.0, damping: float = 0.5) -> Workload:
+    """The ``datalog`` generator's distributions at any size, vectorised (a different random stream
+    from ``datalog``). About num_vars variables: T tuples and 0.75 T rules, each rule with a clause
+    variable and an AND over 2-3 distinct lower-index body tuples; a NOISY_OR per distinct head."""
+    rng = np.random.default_rng(seed)
+    num_tuples = max(8, int(round(num_vars / 1.75)))
+    num_rules = max(1, num_vars - num_tuples)
+    lo_head = max(3, body[1])
+    heads = np.sort(rng.integers(lo_head, num_tuples, num_rules)).astype(np.int64)
+    bsize = rng.integers(body[0], body[1] + 1, num_rules)
+    nb = body[1]
+    bodies = (rng.random((num_rules, nb)) * heads[:, None]).astype(np.int64)
+    mask = np.arange(nb)[None, :] < bsize[:, None]
+    for _ in range(200):
+        srt = np.sort(np.where(mask, bodies, -1 - np.arange(nb)[None, :]), axis=1)
+        bad = np.flatnonzero(((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] >= 0)).any(axis=1))
+        if len(bad) == 0:
+            break
+        bodies[bad] = (rng.random((len(bad), nb)) * heads[bad, None]).astype(np.int64)
+    nv = num_tuples + num_rules
+    and_deg = bsize + 1
+    and_off = _csr(and_deg)
+    and_vars = np.empty(int(and_deg.sum()), dtype=np.int64)
+    for j in range(nb):
+        sel = bsize > j
+        and_vars[and_off[:-1][sel] + j] = bodies[sel, j]
+    and_vars[and_off[1:] - 1] = num_tuples + np.arange(num_rules)
+    p = rng.uniform(rule_p[0], rule_p[1], num_rules)
+    uniq, start, counts = np.unique(heads, return_index=True, return_counts=True)
+    no_deg = counts + 1
+    no_off = _csr(no_deg)
+    no_vars = np.empty(int(no_deg.sum()), dtype=np.int64)
+    no_ep = np.zeros(int(no_deg.sum()))
+    hidx = np.repeat(np.arange(len(uniq)), counts)
+    dst = no_off[hidx] + (np.arange(num_rules) - start[hidx])
+    no_vars[dst] = num_tuples + np.arange(num_rules)
+    no_ep[dst] = p
+    no_vars[no_off[1:] - 1] = uniq
+    npri = int(round(prior_frac * num_tuples))
+    pv = np.sort(rng.choice(num_tuples, size=npri, replace=False))
+    pp = rng.uniform(prior_p[0], prior_p[1], npri)
+    fac_type = np.concatenate([np.full(num_rules, AND), np.full(len(uniq), NOISY_OR),
+                               np.full(npri, PRIOR)]).astype(np.uint8)
+    deg = np.concatenate([and_deg, no_deg, np.ones(npri, dtype=np.int64)])
+    w = Workload(num_vars=nv, fac_off=_csr(deg), edge_var=np.concatenate([and_vars, no_vars, pv]).astype(np.int32),
+                 fac_type=fac_type, fac_param=np.concatenate([np.zeros(num_rules + len(uniq)), pp]),
+                 edge_param=np.concatenate([np.zeros(len(and_vars)), no_ep, np.zeros(npri)]), edge_rank=None,
+                 evidence=np.full(nv, -1, dtype=np.int8), max_iters=max_iters, tol=tol, damping=damping,
+                 name="datalog")
+    w.meta = dict(seed=seed, num_tuples=num_tuples, num_rules=num_rules, num_heads=len(uniq))
+    return w
+
+
+@dataclass
+class Query:
+    """One request of the serving mix: a graph, its arrival time and its first evidence clamps."""
+    graph: Workload
+    arrival_s: float
+    ev_vars: np.ndarray
+    ev_vals: np.ndarray
+
+
+def serving_mix(seed: int = 0, num_queries: int = 512, min_vars: int = 1000, max_vars: int = 500_000,
+                rate_qps: float = 200.0, max_iters: int = 100, tol: float = 1e-6) -> list:
+    """Serving workload: ``num_queries`` graphs with sizes log-uniform in [min_vars, max_vars], half
+    Datalog-shaped (flooding, damping 0.5) and half SmartFL-shaped (width 400, ceil(V/400) layers,
+    forward-backward ranks, 2% consistent clamps), arriving as a Poisson process at ``rate_qps``.
+    Every run uses ``tol`` and at most ``max_iters`` iterations."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(min_vars), np.log(max_vars), num_queries)).astype(np.int64)
+    kinds = rng.random(num_queries) < 0.5
+    arrivals = np.cumsum(rng.exponential(1.0 / rate_qps, num_queries))
+    out = []
+    for q in range(num_queries):
+        gseed = int(rng.integers(0, 2**31))
+        if kinds[q]:
+            w = datalog_scaled(gseed, int(sizes[q]), max_iters=max_iters, tol=tol)
+        else:
+            w = smartfl(gseed, levels=max(2, int(-(-sizes[q] // 400))), width=400, max_iters=max_iters, tol=tol)
+        ev = w.evidence
+        v = np.flatnonzero(ev >= 0).astype(np.int32)
+        out.append(Query(w, float(arrivals[q]), v, ev[v].astype(np.int8)))
+    return out
+
+
+def requery_clamps(w: Workload, marginals: np.ndarray, seed: int) -> tuple:
+    """1-10 new clamps for a warm re-query: random variables set to a value of the consistent world
+    (SmartFL-shaped graphs) or drawn from the current marginal (Datalog-shaped graphs)."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 11))
+    v = np.sort(rng.choice(w.num_vars, size=min(k, w.num_vars), replace=False)).astype(np.int32)
+    if "world" in w.meta:
+        x = w.meta["world"][v].astype(np.int8)
+    else:
+        x = (rng.random(len(v)) < marginals[v]).astype(np.int8)
+    return v, x
+
+
 def config(name: str, seed: int = 0, scale: float = 1.0) -> Workload:
     """The five benchmark configurations by short name (C1..C5); ``scale`` shrinks C2/C3/C5 for
     tests that must finish quickly."""

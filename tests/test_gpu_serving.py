@@ -28,10 +28,12 @@ def _say(*a):
 
 
 def _graphs():
-    # convergent, non-chaotic instances of both generators at a few sizes
+    # convergent, non-chaotic instances of both generators at a few sizes; the last one has a
+    # flooding level of ~20k edges, too wide for one workgroup, so the server steps it with the
+    # LEVELS executor beside the persistent launch of the others
     return [W.smartfl(4, levels=30, width=60, max_iters=100), W.smartfl(11, levels=30, width=60, max_iters=100),
             W.datalog(1, num_tuples=600, num_rules=450), W.datalog(2, num_tuples=2000, num_rules=1500),
-            W.smartfl(13, levels=30, width=60, max_iters=100)]
+            W.smartfl(13, levels=30, width=60, max_iters=100), W.datalog(3, num_tuples=8000, num_rules=6000)]
 
 
 def _requests(ws, rng):
@@ -58,11 +60,10 @@ def test_server_mixed_stream_matches_alone_and_oracle(precision):
     rng = np.random.default_rng(0)
     reqs = _requests(ws, rng)
     params = [(w.max_iters, w.tol, w.damping) for w in ws]
-    # alone: each graph's requests in order on its own handle, one at a time
+    # alone: each graph's requests in order on its own handle, one at a time (same executor
+    # choice as the server's)
     alone = []
-    for gi, v, x in reqs:
-        pass
-    solo_h = [F.Graph.from_workload(w, precision=precision, executor="persistent") for w in ws]
+    solo_h = [F.Graph.from_workload(w, precision=precision) for w in ws]
     for h in solo_h:
         h.evidence_clear()
     for gi, v, x in reqs:
@@ -102,6 +103,7 @@ def test_server_mixed_stream_matches_alone_and_oracle(precision):
         _say(precision, i, w.name, "iters", st_srv["iterations"], st_alone["iterations"], ost["iterations"],
              "alone", d_alone, "oracle", d_or, "lat ms %.1f" % lat)
         assert st_srv["iterations"] == st_alone["iterations"]
+        assert st_srv["executor"] == st_alone["executor"] == (F.EXEC_LEVELS if gi == len(ws) - 1 else F.EXEC_PERSISTENT)
         assert d_alone <= (1e-12 if precision == "fp64" else 1e-6)
         assert d_or <= TOL[precision]
     for h in hs + solo_h:
