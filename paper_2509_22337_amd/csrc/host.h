@@ -55,8 +55,10 @@ struct HostPlan {
     std::vector<int32_t> var_list[VB_COUNT];
     std::vector<int32_t> var_lvl_off[VB_COUNT];
     std::vector<int32_t> init_var[VB_COUNT];
-    // task records of the thread buckets, in the order of fac_list / var_list (12 / 8 int32 each)
+    // task records of the thread buckets (12 / 8 int32 each): per level sorted by degree, each
+    // degree group padded to a multiple of 64 records; frec_off / vrec_off delimit the levels
     std::vector<int32_t> frec, vrec;
+    std::vector<int32_t> frec_off, vrec_off;
     double bytes_per_iter = 0.0;   // algorithmic bytes of one iteration
     int64_t updates_per_iter = 0;  // non-PRIOR edges written per iteration
 

@@ -292,52 +292,102 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         // list entry, offsets, phi, belief write; per edge: edge id and message
         for (int32_t v : lst) bytes_per_iter += 4 + 8 + 2 * sizeof(Belief) + double(g.var_deg[v]) * (4 + msg_bytes);
     }
+    auto fdeg = [&](int32_t a) { return int32_t(g.fac_off[a + 1] - g.fac_off[a]); };
     for (int b = 0; b < FB_COUNT; ++b) {
         fac_list[b].clear();
         fac_lvl_off[b].assign(1, 0);
         for (int32_t L = 0; L < exec_levels; ++L) {
             auto &src = fac_by_level[L * FB_COUNT + b];
-            // group factors of one type together so a wavefront mostly follows one code path
-            std::stable_sort(src.begin(), src.end(),
-                             [&](int32_t x, int32_t y) { return g.fac_type[x] < g.fac_type[y]; });
+            // thread bucket: by degree, then type (a wavefront follows one code path); wider
+            // buckets: largest first, so the longest tasks start early
+            if (b == FB_THREAD)
+                std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
+                    int dx = fdeg(x), dy = fdeg(y);
+                    if (dx != dy) return dx < dy;
+                    if (g.fac_type[x] != g.fac_type[y]) return g.fac_type[x] < g.fac_type[y];
+                    return x < y;
+                });
+            else
+                std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
+                    int dx = fdeg(x), dy = fdeg(y);
+                    return dx != dy ? dx > dy : x < y;
+                });
             fac_list[b].insert(fac_list[b].end(), src.begin(), src.end());
             fac_lvl_off[b].push_back(int32_t(fac_list[b].size()));
         }
     }
+    auto vkey = [&](int32_t v) { return std::min<int32_t>(g.var_deg[v], kVarRecEdges); };
     for (int b = 0; b < VB_COUNT; ++b) {
         var_list[b].clear();
         var_lvl_off[b].assign(1, 0);
         for (int32_t L = 0; L < exec_levels; ++L) {
             auto &src = var_by_level[L * VB_COUNT + b];
+            if (b == VB_THREAD)
+                std::stable_sort(src.begin(), src.end(), [&](int32_t x, int32_t y) { return vkey(x) < vkey(y); });
             var_list[b].insert(var_list[b].end(), src.begin(), src.end());
             var_lvl_off[b].push_back(int32_t(var_list[b].size()));
         }
         init_var[b].clear();
     }
     for (int32_t v = 0; v < g.V; ++v) init_var[g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE].push_back(v);
-    // records: factor {b, d | type << 8 | active << 16, id, u0..u7, 0}; variable {v, row, degree, e0..e4}
-    frec.assign(fac_list[FB_THREAD].size() * 12, 0);
-    for (int32_t L = 0; L < exec_levels; ++L)
-        for (int32_t i = fac_lvl_off[FB_THREAD][L]; i < fac_lvl_off[FB_THREAD][L + 1]; ++i) {
-            int32_t a = fac_list[FB_THREAD][i];
-            int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
-            int32_t *r = &frec[size_t(i) * 12];
-            unsigned mask = 0;
-            for (int64_t k = 0; k < d; ++k)
-                if (edge_exec_level[b + k] == L) mask |= 1u << k;
-            r[0] = int32_t(b);
-            r[1] = int32_t(d) | (int32_t(g.fac_type[a]) << 8) | int32_t(mask << 16);
-            r[2] = a;
-            for (int k = 0; k < 8; ++k) r[3 + k] = k < d ? g.edge_var[b + k] : 0;
+    // records: factor {b, d | type << 8 | active << 16, id, u0..u7, 0}; variable {v, row, degree,
+    // e0..e4}. A degree group is padded to a multiple of 64 with copies of its first record that
+    // write nothing (factor: no active edge; variable: padding flag).
+    frec.clear();
+    frec_off.assign(1, 0);
+    for (int32_t L = 0; L < exec_levels; ++L) {
+        const int32_t i0 = fac_lvl_off[FB_THREAD][L], i1 = fac_lvl_off[FB_THREAD][L + 1];
+        for (int32_t i = i0; i < i1;) {
+            const int32_t d = fdeg(fac_list[FB_THREAD][i]);
+            int32_t j = i;
+            for (; j < i1 && fdeg(fac_list[FB_THREAD][j]) == d; ++j) {
+                int32_t a = fac_list[FB_THREAD][j];
+                int64_t b = g.fac_off[a];
+                int32_t r[12] = {0};
+                unsigned mask = 0;
+                for (int64_t k = 0; k < d; ++k)
+                    if (edge_exec_level[b + k] == L) mask |= 1u << k;
+                r[0] = int32_t(b);
+                r[1] = d | (int32_t(g.fac_type[a]) << 8) | int32_t(mask << 16);
+                r[2] = a;
+                for (int k = 0; k < 8; ++k) r[3 + k] = k < d ? g.edge_var[b + k] : 0;
+                frec.insert(frec.end(), r, r + 12);
+            }
+            const size_t first = frec.size() - size_t(j - i) * 12;
+            while ((frec.size() / 12) % 64) {
+                std::vector<int32_t> r(frec.begin() + first, frec.begin() + first + 12);
+                r[1] &= 0xffff;  // no active edge
+                frec.insert(frec.end(), r.begin(), r.end());
+            }
+            i = j;
         }
-    vrec.assign(var_list[VB_THREAD].size() * 8, 0);
-    for (size_t i = 0; i < var_list[VB_THREAD].size(); ++i) {
-        int32_t v = var_list[VB_THREAD][i];
-        int32_t *r = &vrec[i * 8];
-        r[0] = v;
-        r[1] = g.var_off[v];
-        r[2] = g.var_deg[v];
-        for (int j = 0; j < kVarRecEdges; ++j) r[3 + j] = j < g.var_deg[v] ? g.var_edge[g.var_off[v] + j] : 0;
+        frec_off.push_back(int32_t(frec.size() / 12));
+    }
+    vrec.clear();
+    vrec_off.assign(1, 0);
+    for (int32_t L = 0; L < exec_levels; ++L) {
+        const int32_t i0 = var_lvl_off[VB_THREAD][L], i1 = var_lvl_off[VB_THREAD][L + 1];
+        for (int32_t i = i0; i < i1;) {
+            const int32_t key = vkey(var_list[VB_THREAD][i]);
+            int32_t j = i;
+            for (; j < i1 && vkey(var_list[VB_THREAD][j]) == key; ++j) {
+                int32_t v = var_list[VB_THREAD][j];
+                int32_t r[8] = {0};
+                r[0] = v;
+                r[1] = g.var_off[v];
+                r[2] = g.var_deg[v];
+                for (int q = 0; q < kVarRecEdges; ++q) r[3 + q] = q < g.var_deg[v] ? g.var_edge[g.var_off[v] + q] : 0;
+                vrec.insert(vrec.end(), r, r + 8);
+            }
+            const size_t first = vrec.size() - size_t(j - i) * 8;
+            while ((vrec.size() / 8) % 64) {
+                std::vector<int32_t> r(vrec.begin() + first, vrec.begin() + first + 8);
+                r[2] |= 1 << 30;  // padding: computes, stores nothing
+                vrec.insert(vrec.end(), r.begin(), r.end());
+            }
+            i = j;
+        }
+        vrec_off.push_back(int32_t(vrec.size() / 8));
     }
 }
 

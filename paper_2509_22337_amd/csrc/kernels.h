@@ -558,168 +558,268 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
 }
 
 // ------------------------------------------------------------------------------------------------
-// Record-based processing for the persistent executor. The host packs, per level, one record per
-// factor task with everything static already resolved (edge range, degree, type, the level's active
-// edges, variable ids) and one per variable task (row start, degree, first edge ids), so that a
-// thread issues all of a task's dynamic loads (messages, beliefs) at once.
+// Record-based thread tasks (both executors). The host packs, per level, one record per factor of
+// degree <= 8 and one per variable of degree <= 64 with everything static already resolved (edge
+// range, degree, type, the level's active edges, variable ids, first edge ids), so that a thread
+// issues all of a task's dynamic loads (messages, beliefs) at once. Records of a level are sorted
+// by degree and every degree group is padded to a multiple of 64, so the 64 records a wavefront
+// takes share one degree: the degree switch below is then uniform and each case loads exactly its
+// degree's operands.
 // ------------------------------------------------------------------------------------------------
 
-// One factor of degree d <= 8 from values in registers: lo[k] the old message of edge b + k,
-// vf[k] its variable-to-factor message, nl[k] whether that is the null message. Bit k of `active`
-// selects the edges the level writes.
-template <class P, bool DAMP>
-__device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int d,
-                                             int32_t b, unsigned active, const Pair<typename P::V> &fp,
-                                             const typename P::S (&lo)[8], const typename P::S (&vf)[8],
-                                             const bool (&nl)[8], const Pair<typename P::V> (&ep)[8], Acc &acc) {
-    using S = typename P::S;
+// One factor of degree D from values in registers: lo[k] the old message of edge b + k, vf[k] its
+// variable-to-factor message, nl[k] whether that is the null message. Bit k of `active` selects
+// the edges the level writes.
+template <class P, bool DAMP, int D>
+__device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int32_t b,
+                                             unsigned active, const Pair<typename P::V> &fp,
+                                             const typename P::S (&lo)[D], const typename P::S (&vf)[D],
+                                             const bool (&nl)[D], const Pair<typename P::V> (&ep)[D], Acc &acc) {
     using V = typename P::V;
-    if (type == T_NOT) {
+    if constexpr (D == 2) {
+        if (type == T_NOT) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            if (!((active >> k) & 1u)) continue;
-            V m0, m1;
-            P::leaf(-vf[1 - k], m0, m1);
-            store_msg<P, DAMP>(g, b + k, lo[k], m0, m1, nl[1 - k], acc);
+            for (int k = 0; k < 2; ++k) {
+                if (!((active >> k) & 1u)) continue;
+                V m0, m1;
+                P::leaf(-vf[1 - k], m0, m1);
+                store_msg<P, DAMP>(g, b + k, lo[k], m0, m1, nl[1 - k], acc);
+            }
+            return;
         }
-        return;
     }
-    const int n = d - 1;
-    // head values, selected without dynamic register indexing
-    S vfh = (S)0, loh = (S)0;
-    bool nlh = false;
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k == n) {
-            vfh = vf[k];
-            loh = lo[k];
-            nlh = nl[k];
-        }
+    constexpr int n = D - 1;
     V my0 = P::zero(), my1 = P::zero();
-    if (!nlh) P::leaf(vfh, my0, my1);
-    HF<V> lf[7];
+    if (!nl[n]) P::leaf(vf[n], my0, my1);
+    HF<V> lf[n];
     int nnull = 0;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        if (k < n) {
-            lf[k] = identity<P>();
-            if (!nl[k]) {
-                V m0, m1;
-                P::leaf(vf[k], m0, m1);
-                lf[k] = make_leaf<P>(type, m0, m1, ep[k]);
-            } else {
-                ++nnull;
-            }
+    for (int k = 0; k < n; ++k) {
+        lf[k] = identity<P>();
+        if (!nl[k]) {
+            V m0, m1;
+            P::leaf(vf[k], m0, m1);
+            lf[k] = make_leaf<P>(type, m0, m1, ep[k]);
+        } else {
+            ++nnull;
         }
     }
     HF<V> pre = identity<P>();
     if (type == T_NOISY_OR) pre = {fp.b, fp.a};  // leak
     HF<V> tot = pre;
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
-        if (k < n) tot = combine<P>(tot, lf[k]);
+    for (int k = 0; k < n; ++k) tot = combine<P>(tot, lf[k]);
     if ((active >> n) & 1u) {
         V o0, o1;
         head_msg<P>(type, tot, fp, o0, o1);
-        g.msg[b + n] = finish_msg<P, DAMP>(g, loh, o0, o1, nnull > 0, acc);
+        g.msg[b + n] = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
     }
-    HF<V> sx[7];
+    HF<V> sx[n];
     HF<V> run = identity<P>();
 #pragma unroll
-    for (int k = 6; k >= 0; --k)
-        if (k < n) {
-            sx[k] = run;
-            run = combine<P>(lf[k], run);
-        }
+    for (int k = n - 1; k >= 0; --k) {
+        sx[k] = run;
+        run = combine<P>(lf[k], run);
+    }
     run = pre;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        if (k < n) {
-            if ((active >> k) & 1u) {
-                HF<V> xo = combine<P>(run, sx[k]);
-                V o0, o1;
-                input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
-                int others_null = nnull - (nl[k] ? 1 : 0) + (nlh ? 1 : 0);
-                g.msg[b + k] = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
-            }
-            run = combine<P>(run, lf[k]);
+    for (int k = 0; k < n; ++k) {
+        if ((active >> k) & 1u) {
+            HF<V> xo = combine<P>(run, sx[k]);
+            V o0, o1;
+            input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
+            int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
+            g.msg[b + k] = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
         }
+        run = combine<P>(run, lf[k]);
     }
 }
 
-// Loads of one factor of degree <= 8 (edge range b, d) whose variables u[] are known, all issued
-// before any is used: slots past the degree re-read slot 0 and are ignored.
-template <class P, bool DAMP>
+// Loads of one factor of degree D (edges b .. b+D-1, variables u[]), all issued before any is used.
+template <class P, bool DAMP, int D>
 __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
-                                                     int d, int type, int32_t fac, unsigned active,
-                                                     const int32_t (&u)[8], Acc &acc) {
+                                                     int type, int32_t fac, unsigned active, const int32_t *u,
+                                                     Acc &acc) {
     using S = typename P::S;
     using V = typename P::V;
-    S lo[8];
-    Belief B[8];
+    S lo[D];
+    Belief B[D];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int kk = k < d ? k : 0;
-        lo[k] = g.msg[b + kk];
-        B[k] = g.bel.ld(u[kk]);
+    for (int k = 0; k < D; ++k) {
+        lo[k] = g.msg[b + k];
+        B[k] = g.bel.ld(u[k]);
     }
-    Pair<V> ep[8];
+    Pair<V> ep[D];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) ep[k] = {P::zero(), P::one()};
+    for (int k = 0; k < D; ++k) ep[k] = {P::zero(), P::one()};
     if (type == T_NOISY_OR) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) ep[k] = g.epar.ld(b + (k < d ? k : 0));
+        for (int k = 0; k < D - 1; ++k) ep[k] = g.epar.ld(b + k);
     }
     Pair<V> fp = {P::zero(), P::one()};
     if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar.ld(fac);
-    S vf[8];
-    bool nl[8];
+    S vf[D];
+    bool nl[D];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) vf[k] = v2f<P>(B[k], lo[k], nl[k]);
-    factor_local<P, DAMP>(g, type, d, b, active, fp, lo, vf, nl, ep, acc);
+    for (int k = 0; k < D; ++k) vf[k] = v2f<P>(B[k], lo[k], nl[k]);
+    factor_local<P, DAMP, D>(g, type, b, active, fp, lo, vf, nl, ep, acc);
 }
 
 template <class P, bool DAMP>
 __device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc) {
     const int d = r.meta & 0xff, type = (r.meta >> 8) & 0xff;
     const unsigned active = (unsigned)(r.meta >> 16) & 0xffu;
-    const int32_t u[8] = {r.u[0], r.u[1], r.u[2], r.u[3], r.u[4], r.u[5], r.u[6], r.u[7]};
-    factor_fetch_compute<P, DAMP>(g, r.b, d, type, r.fac, active, u, acc);
+    switch (d) {
+    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc); break;
+    default: break;
+    }
 }
 
-// A factor of degree <= 8 from the factor list (wide executor): structure loads, then the same
-// fetch-then-compute as the records.
-template <class P, bool ALL_ACTIVE, bool DAMP>
-__device__ __forceinline__ void factor_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int level,
-                                              Acc &acc) {
-    const int32_t b = g.fac_off[a];
-    const int d = g.fac_off[a + 1] - b;
-    const int type = g.fac_type[a];
-    int32_t u[8];
-    unsigned active = 0;
+// A variable record with C edge ids in the record (C = min(degree, 5)); edges past the fifth come
+// from var_edge. Padding records (bit 30 of cnt) recompute their group's first belief and do not
+// store it.
+template <class P, int C>
+__device__ __forceinline__ void var_rec_c(const DevGraph<typename P::S, typename P::V> &g, const VarRec &r, int cnt,
+                                          bool pad) {
+    using S = typename P::S;
+    Belief B = g.phi.ld(r.v);
+    S m[C > 0 ? C : 1];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int kk = k < d ? k : 0;
-        u[k] = g.edge_var[b + kk];
-        bool on = ALL_ACTIVE || g.edge_level[b + kk] == level;
-        active |= (on && k < d) ? (1u << k) : 0u;
-    }
-    factor_fetch_compute<P, DAMP>(g, b, d, type, a, active, u, acc);
+    for (int j = 0; j < C; ++j) m[j] = g.msg[r.e[j]];
+#pragma unroll
+    for (int j = 0; j < C; ++j) belief_add<P>(B, m[j]);
+    if (C == kVarRecEdges)
+        for (int32_t j = kVarRecEdges; j < cnt; ++j) belief_add<P>(B, g.msg[g.var_edge[r.start + j]]);
+    if (!pad) g.bel.st(r.v, B);
 }
 
 template <class P>
 __device__ __forceinline__ void var_rec(const DevGraph<typename P::S, typename P::V> &g, const VarRec &r) {
+    const int cnt = r.cnt & 0xffff;
+    const bool pad = (r.cnt >> 30) & 1;
+    switch (cnt < kVarRecEdges ? cnt : kVarRecEdges) {
+    case 0: var_rec_c<P, 0>(g, r, cnt, pad); break;
+    case 1: var_rec_c<P, 1>(g, r, cnt, pad); break;
+    case 2: var_rec_c<P, 2>(g, r, cnt, pad); break;
+    case 3: var_rec_c<P, 3>(g, r, cnt, pad); break;
+    case 4: var_rec_c<P, 4>(g, r, cnt, pad); break;
+    default: var_rec_c<P, kVarRecEdges>(g, r, cnt, pad); break;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// One factor of n = d - 1 inputs (8 < d <= 257) by one wavefront. Lane j owns the contiguous inputs
+// [j c, j c + c) with c = ceil(n / 64) <= C, keeps their leaves in registers, and issues every load
+// (its inputs, clamped to the last one so each address is valid, and the head) before the scan.
+// ------------------------------------------------------------------------------------------------
+template <class P, int C, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_wave_c(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int32_t b,
+                                              int32_t d, int type, int lane, int level, Acc &acc) {
     using S = typename P::S;
-    const int32_t cnt = r.cnt;
-    Belief B = g.phi.ld(r.v);
-    S m[kVarRecEdges];
+    using V = typename P::V;
+    const int32_t n = d - 1;
+    const int32_t c = (n + 63) >> 6;
+    const int32_t i0 = min(n, lane * c), i1 = min(n, i0 + c);
+    const int32_t eh = b + n;
+    S lo[C];
+    int32_t u[C];
 #pragma unroll
-    for (int j = 0; j < kVarRecEdges; ++j) m[j] = g.msg[r.e[j < cnt ? j : 0]];
+    for (int k = 0; k < C; ++k) {
+        const int32_t e = b + min(i0 + k, n - 1);
+        lo[k] = g.msg[e];
+        u[k] = g.edge_var[e];
+    }
+    const S loh = g.msg[eh];
+    const int32_t uh = g.edge_var[eh];
+    Belief B[C];
 #pragma unroll
-    for (int j = 0; j < kVarRecEdges; ++j)
-        if (j < cnt) belief_add<P>(B, m[j]);
-    for (int32_t j = kVarRecEdges; j < cnt; ++j) belief_add<P>(B, g.msg[g.var_edge[r.start + j]]);
-    g.bel.st(r.v, B);
+    for (int k = 0; k < C; ++k) B[k] = g.bel.ld(u[k]);
+    const Belief Bh = g.bel.ld(uh);
+    Pair<V> fp = {P::zero(), P::one()};
+    if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar.ld(a);
+    Pair<V> ep[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) ep[k] = {P::zero(), P::one()};
+    if (type == T_NOISY_OR) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) ep[k] = g.epar.ld(b + min(i0 + k, n - 1));
+    }
+    bool null_h;
+    const S vfh = v2f<P>(Bh, loh, null_h);
+    V my0 = P::zero(), my1 = P::zero();
+    if (!null_h) P::leaf(vfh, my0, my1);
+    HF<V> lf[C];
+    bool ln[C];
+    int nnull = 0;
+    HF<V> agg = identity<P>();
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const bool mine = i0 + k < i1;
+        const S vf = v2f<P>(B[k], lo[k], ln[k]);
+        lf[k] = identity<P>();
+        if (mine && !ln[k]) {
+            V m0, m1;
+            P::leaf(vf, m0, m1);
+            lf[k] = make_leaf<P>(type, m0, m1, ep[k]);
+        }
+        nnull += (mine && ln[k]) ? 1 : 0;
+        agg = combine<P>(agg, lf[k]);
+    }
+    HF<V> init = identity<P>();
+    if (type == T_NOISY_OR) init = {fp.b, fp.a};  // the leak: fires with probability leak
+    HF<V> pre, suf, tot;
+    int ntot;
+    TeamScan<P, 64>::run(agg, nnull, init, pre, suf, tot, ntot, nullptr);
+    if (lane == 0 && is_active<ALL_ACTIVE>(g.edge_level, eh, level)) {
+        V o0, o1;
+        head_msg<P>(type, tot, fp, o0, o1);
+        store_msg<P, DAMP>(g, eh, loh, o0, o1, ntot > 0, acc);
+    }
+    HF<V> sx[C];
+    HF<V> run = suf;
+#pragma unroll
+    for (int k = C - 1; k >= 0; --k) {
+        sx[k] = run;
+        run = combine<P>(lf[k], run);
+    }
+    run = pre;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int32_t e = b + i0 + k;
+        if (i0 + k < i1 && is_active<ALL_ACTIVE>(g.edge_level, e, level)) {
+            HF<V> xo = combine<P>(run, sx[k]);
+            V o0, o1;
+            input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
+            int others_null = ntot - (ln[k] ? 1 : 0) + (null_h ? 1 : 0);
+            store_msg<P, DAMP>(g, e, lo[k], o0, o1, others_null > 0, acc);
+        }
+        run = combine<P>(run, lf[k]);
+    }
+}
+
+template <class P, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_wave(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int lane,
+                                            int level, Acc &acc) {
+    const int32_t b = g.fac_off[a];
+    const int32_t d = g.fac_off[a + 1] - b;
+    const int type = g.fac_type[a];
+    if (type == T_NOT) {  // degree 2: never in this bucket, kept for safety
+        if (lane == 0) factor_not<P, ALL_ACTIVE, DAMP>(g, b, level, acc);
+        return;
+    }
+    const int32_t c = (d - 1 + 63) >> 6;
+    if (c <= 1)
+        factor_wave_c<P, 1, ALL_ACTIVE, DAMP>(g, a, b, d, type, lane, level, acc);
+    else if (c <= 2)
+        factor_wave_c<P, 2, ALL_ACTIVE, DAMP>(g, a, b, d, type, lane, level, acc);
+    else
+        factor_wave_c<P, 4, ALL_ACTIVE, DAMP>(g, a, b, d, type, lane, level, acc);
 }
 
 }  // namespace fastlbp

@@ -93,7 +93,7 @@ struct RunState {
 
 // Degree buckets. Factor degree d = inputs + head.
 constexpr int kThreadMaxDeg = 8;     // one thread per factor
-constexpr int kWaveMaxDeg = 1025;    // one wavefront per factor: 64 lanes x 16 inputs + head
+constexpr int kWaveMaxDeg = 257;     // one wavefront per factor: 64 lanes x up to 4 inputs + head
 constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 1024 x 16 + head
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
 constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record (VarRec::e)
@@ -133,7 +133,7 @@ struct alignas(16) FacRec {
 };
 
 struct alignas(16) VarRec {
-    int32_t v, start, cnt;  // variable, first position in var_edge, degree
+    int32_t v, start, cnt;  // variable, first position in var_edge, degree | (padding record) << 30
     int32_t e[5];           // its first edges (the rest from var_edge)
 };
 
@@ -146,7 +146,8 @@ struct DevPlan {
     GPtr<const int32_t> var_lvl_off[VB_COUNT];  // [num_levels+1]
     GPtr<const int32_t> init_var[VB_COUNT];
     int32_t init_var_count[VB_COUNT];
-    // per-level task records of the thread buckets (persistent executor)
+    // per-level task records of the thread buckets, sorted by degree, each degree group padded to
+    // a multiple of 64 records (so every level starts at a multiple of 64)
     GPtr<const FacRec> frec;
     GPtr<const int32_t> frec_off;  // [num_levels+1]
     GPtr<const VarRec> vrec;

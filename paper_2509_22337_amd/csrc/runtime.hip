@@ -8,6 +8,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fastlbp.h"
@@ -35,13 +36,16 @@ __device__ __forceinline__ void flush_acc(Acc acc, RunState *st) {
     }
 }
 
-template <class P, bool ALL, bool DAMP>
-__global__ __launch_bounds__(256) void k_fac_thread(DevGraph<typename P::S, typename P::V> g, const int32_t *list,
-                                                    int32_t count, int32_t level, RunState *st) {
+// Factors of degree <= 8 from the level's task records (records of a level start at a multiple of
+// 64 and the grid stride is a multiple of 64, so a wavefront's records share one degree).
+template <class P, bool DAMP>
+__global__ __launch_bounds__(256) void k_fac_rec(DevGraph<typename P::S, typename P::V> g, const FacRec *recs,
+                                                 int32_t count, RunState *st) {
     if (st->done) return;
     Acc acc = {0.0, 0u};
+    const GPtr<const FacRec> R(recs);
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-        factor_thread<P, ALL, DAMP>(g, list[i], level, acc);
+        factor_rec<P, DAMP>(g, R.ld_stream(i), acc);
     flush_acc(acc, st);
 }
 
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_fac_wave(DevGraph<typename P::S, typena
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * (blockDim.x >> 6);
     for (int32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < count; i += waves)
-        factor_team<P, 64, 16, ALL, DAMP>(g, list[i], lane, level, acc, nullptr);
+        factor_wave<P, ALL, DAMP>(g, list[i], lane, level, acc);
     flush_acc(acc, st);
 }
 
@@ -81,6 +85,15 @@ __global__ __launch_bounds__(256) void k_var_thread(DevGraph<typename P::S, type
     if (st && st->done) return;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         var_thread<P>(g, list[i]);
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_var_rec(DevGraph<typename P::S, typename P::V> g, const VarRec *recs,
+                                                 int32_t count, const RunState *st) {
+    if (st->done) return;
+    const GPtr<const VarRec> R(recs);
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        var_rec<P>(g, R.ld_stream(i));
 }
 
 template <class P>
@@ -200,8 +213,7 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
             if (TEAMS) {
                 const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
                 int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
-                for (int32_t i = o0 + w; i < o1; i += NW)
-                    factor_team<P, 64, 16, false, DAMP>(g, lst[i], lane, L, acc, nullptr);
+                for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
             }
             if (TEAMS) {
                 const GPtr<const int32_t> lst = plan.fac_list[FB_BLOCK];
@@ -321,7 +333,7 @@ struct Plan {
     int32_t *edge_level = nullptr;
     int32_t *fac_list[FB_COUNT] = {}, *fac_lvl_off[FB_COUNT] = {};
     int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
-    int32_t *frec = nullptr, *vrec = nullptr;
+    int32_t *frec = nullptr, *vrec = nullptr, *frec_off = nullptr, *vrec_off = nullptr;
     bool teams() const { return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty(); }
     DevPlan view() const {
         DevPlan p;
@@ -338,9 +350,9 @@ struct Plan {
             p.init_var_count[b] = int32_t(hp.init_var[b].size());
         }
         p.frec = (const FacRec *)frec;
-        p.frec_off = fac_lvl_off[FB_THREAD];
+        p.frec_off = frec_off;
         p.vrec = (const VarRec *)vrec;
-        p.vrec_off = var_lvl_off[VB_THREAD];
+        p.vrec_off = vrec_off;
         return p;
     }
 };
@@ -510,6 +522,8 @@ static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, h
     }
     P->frec = P->pool.upload(P->hp.frec, s);
     P->vrec = P->pool.upload(P->hp.vrec, s);
+    P->frec_off = P->pool.upload(P->hp.frec_off, s);
+    P->vrec_off = P->pool.upload(P->hp.vrec_off, s);
     return P;
 }
 
@@ -563,9 +577,9 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
     hipStream_t s = g->L.stream;
     for (int32_t L = 0; L < pl.exec_levels; ++L) {
         int32_t o, n;
-        o = pl.fac_lvl_off[FB_THREAD][L];
-        n = pl.fac_lvl_off[FB_THREAD][L + 1] - o;
-        if (n) k_fac_thread<PP, ALL, DAMP><<<grid_for(n, 256), 256, 0, s>>>(dg, P.fac_list[FB_THREAD] + o, n, L, g->st);
+        o = pl.frec_off[L];
+        n = pl.frec_off[L + 1] - o;
+        if (n) k_fac_rec<PP, DAMP><<<grid_for(n, 256), 256, 0, s>>>(dg, (const FacRec *)P.frec + o, n, g->st);
         o = pl.fac_lvl_off[FB_WAVE][L];
         n = pl.fac_lvl_off[FB_WAVE][L + 1] - o;
         if (n) k_fac_wave<PP, ALL, DAMP><<<grid_for(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
@@ -574,9 +588,9 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         if (n)
             k_fac_block<PP, ALL, DAMP, block_threads<PP>()><<<std::min(n, 4096), block_threads<PP>(), 0, s>>>(
                 dg, P.fac_list[FB_BLOCK] + o, n, L, g->st);
-        o = pl.var_lvl_off[VB_THREAD][L];
-        n = pl.var_lvl_off[VB_THREAD][L + 1] - o;
-        if (n) k_var_thread<PP><<<grid_for(n, 256), 256, 0, s>>>(dg, P.var_list[VB_THREAD] + o, n, g->st);
+        o = pl.vrec_off[L];
+        n = pl.vrec_off[L + 1] - o;
+        if (n) k_var_rec<PP><<<grid_for(n, 256), 256, 0, s>>>(dg, (const VarRec *)P.vrec + o, n, g->st);
         o = pl.var_lvl_off[VB_WAVE][L];
         n = pl.var_lvl_off[VB_WAVE][L + 1] - o;
         if (n) k_var_wave<PP><<<grid_for(n, 4), 256, 0, s>>>(dg, P.var_list[VB_WAVE] + o, n, g->st);
@@ -586,12 +600,8 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
 
 // Workgroup size of the persistent executor: 1024 threads for float32 plans without wavefront or
 // workgroup factors, else 512 (float64 factor code and the team paths need more than the 128
-// registers a 1024-thread workgroup allows). FASTLBP_PERSISTENT_THREADS=512|1024 overrides.
-static int persistent_threads(int precision, bool teams) {
-    const char *e = std::getenv("FASTLBP_PERSISTENT_THREADS");
-    if (e && (std::atoi(e) == 512 || std::atoi(e) == 1024)) return std::atoi(e);
-    return (precision == FASTLBP_FP32 && !teams) ? 1024 : 512;
-}
+// registers a 1024-thread workgroup allows; only the 1024-thread float32 thread-task variant fits).
+static int persistent_threads(int precision, bool teams) { return (precision == FASTLBP_FP32 && !teams) ? 1024 : 512; }
 
 static int choose_executor(const fastlbp_graph *g) {
     int ex = g->opts.executor;
@@ -677,12 +687,15 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     const size_t lds_bytes = sizeof(int32_t) * 2 * size_t(lds_levels + 1);
     HIPCHK(hipEventRecord(lc.k0, s));
 #define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, lds_bytes, s>>>(dd, lds_levels)
-    if (nt == 1024) {
-        if (damp && teams) FASTLBP_LAUNCH(true, true, 1024);
-        else if (damp) FASTLBP_LAUNCH(true, false, 1024);
-        else if (teams) FASTLBP_LAUNCH(false, true, 1024);
-        else FASTLBP_LAUNCH(false, false, 1024);
-    } else {
+    bool launched = false;
+    if constexpr (std::is_same<PP, PolLog32>::value) {
+        if (nt == 1024) {
+            if (damp) FASTLBP_LAUNCH(true, false, 1024);
+            else FASTLBP_LAUNCH(false, false, 1024);
+            launched = true;
+        }
+    }
+    if (!launched) {
         if (damp && teams) FASTLBP_LAUNCH(true, true, 512);
         else if (damp) FASTLBP_LAUNCH(true, false, 512);
         else if (teams) FASTLBP_LAUNCH(false, true, 512);

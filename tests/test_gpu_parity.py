@@ -155,10 +155,13 @@ def test_smartfl_full_size(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_large_fanin_buckets(precision):
-    # noisy-or fan-in up to several thousand: thread, wavefront and workgroup buckets all used
+    # noisy-or fan-in up to several thousand: thread, wavefront (1, 2 and 4 inputs per lane) and
+    # workgroup buckets all used
     w = W.bingo(3, num_tuples=20_000, num_rules=40_000, max_iters=4)
     deg = np.diff(w.fac_off)
-    assert deg.max() > 1025 and ((deg > 8) & (deg <= 1025)).any()
+    assert deg.max() > 257
+    for lo, hi in ((9, 65), (66, 129), (130, 257)):
+        assert ((deg >= lo) & (deg <= hi)).any(), (lo, hi)
     _say("bingo-small", precision, deg.max())
     for executor in ("levels", "persistent"):
         m, msgs, st, _ = _gpu_run(w, precision, executor, max_iters=4, tol=0.0, damping=0.0)
@@ -167,6 +170,53 @@ def test_large_fanin_buckets(precision):
         _say("  ", executor, "err", err)
         assert err <= TOL[precision]
         assert np.abs(msgs - omsg).max() <= (1e-9 if precision == "fp64" else 2e-4)
+
+
+def _fanin_ladder(seed):
+    """One factor of every bucket-boundary degree, each type that takes inputs, over shared
+    variables, with priors and a few clamps."""
+    rng = np.random.default_rng(seed)
+    degs = [2, 3, 8, 9, 10, 64, 65, 66, 67, 128, 129, 130, 131, 256, 257, 258, 259, 1025, 1026, 2049]
+    nv = 3000
+    b = W._Builder(nv)
+    for i, d in enumerate(degs):
+        for t in (W.AND, W.OR, W.IMPLIES, W.NOISY_OR):
+            vs = rng.choice(nv, size=d, replace=False)
+            ep = None
+            fp = 0.0
+            if t == W.NOISY_OR:
+                ep = np.append(rng.uniform(0.05, 0.5, d - 1), 0.0)
+                fp = 0.05
+            if t == W.IMPLIES:
+                fp = 0.9
+            b.add(t, vs, fp, ep)
+    for v in range(nv):
+        b.add(W.PRIOR, [v], float(rng.uniform(0.2, 0.8)))
+    w = b.build(name="ladder", max_iters=3, tol=0.0, damping=0.0)
+    w.edge_rank = None
+    ev = np.full(nv, -1, np.int8)
+    pick = rng.choice(nv, size=30, replace=False)
+    ev[pick] = rng.integers(0, 2, 30)
+    w.evidence = ev
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bucket_boundary_degrees(precision):
+    # every degree at and around the thread / wavefront (1, 2, 4 inputs per lane) / workgroup
+    # boundaries, under flooding and under a ranked schedule that activates a subset of each factor
+    w = _fanin_ladder(21)
+    rng = np.random.default_rng(3)
+    ranks = rng.integers(0, 3, w.num_edges).astype(np.int32)
+    for rk in (None, ranks):
+        for executor in ("levels", "persistent"):
+            m, msgs, st, _ = _gpu_run(w, precision, executor, ranks=rk, max_iters=3, tol=0.0, damping=0.0)
+            om, omsg, ost = oracle.bp(w, 3, 0.0, 0.0, ranks=rk)
+            _say("ladder", precision, executor, "ranked" if rk is not None else "flooding",
+                 np.abs(m - om).max(), np.abs(msgs - omsg).max())
+            assert np.abs(m - om).max() <= TOL[precision]
+            assert np.abs(msgs - omsg).max() <= (1e-9 if precision == "fp64" else 2e-4)
+            assert st["contradictions"] == ost["contradictions"]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
