@@ -11,6 +11,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <type_traits>
 
@@ -77,9 +78,15 @@ struct Pair {
 };
 
 // Per-run state in device memory. Every kernel of a captured iteration returns immediately once
-// `done` is set, so replaying more iterations than needed is harmless.
-struct RunState {
-    unsigned long long rbits;   // residual of the current iteration: max |dP(x=1)|, as double bits
+// `done` is set, so replaying more iterations than needed is harmless. The LEVELS executor's
+// kernels fold their residual and contradiction partials into kRedSlots slots (one per 64-byte
+// line, picked by workgroup index) rather than one word: device-scope atomics to a single address
+// from all XCDs serialise, and at one per workgroup they would dominate a wide level. The
+// end-of-iteration kernel reduces and clears the slots. Only the header (up to `rpart`) is copied
+// to the host.
+constexpr int kRedSlots = 64;
+constexpr int kRedStride = 8;  // 64 bytes between slots
+struct alignas(64) RunState {
     unsigned long long contra;  // messages replaced by uniform during the run
     int32_t iter;               // iterations completed
     int32_t done;               // 1 once converged or max_iters reached
@@ -89,7 +96,10 @@ struct RunState {
     double tol;
     int32_t step_end;           // a launch of the persistent executor returns once iter reaches this
     int32_t pad;
+    alignas(64) unsigned long long rpart[kRedSlots * kRedStride];  // max |dP(x=1)| as double bits
+    unsigned long long cpart[kRedSlots * kRedStride];              // contradictions
 };
+constexpr size_t kRunStateHeader = offsetof(RunState, rpart);
 
 // Degree buckets. Factor degree d = inputs + head.
 constexpr int kThreadMaxDeg = 8;     // one thread per factor

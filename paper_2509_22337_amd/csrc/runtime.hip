@@ -22,7 +22,13 @@ namespace fastlbp {
 // Kernels
 // ------------------------------------------------------------------------------------------------
 
+// Workgroup-wide residual (max) and contradiction count (sum), then one atomic per workgroup into
+// the slot of its index. Every thread of the workgroup must call it.
+template <int NT>
 __device__ __forceinline__ void flush_acc(Acc acc, RunState *st) {
+    constexpr int NW = NT / 64;
+    __shared__ double s_r[NW];
+    __shared__ unsigned int s_c[NW];
     double r = acc.r;
     unsigned int c = acc.contra;
 #pragma unroll
@@ -31,8 +37,18 @@ __device__ __forceinline__ void flush_acc(Acc acc, RunState *st) {
         c += __shfl_xor(c, k, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        if (r > 0.0) atomicMax(&st->rbits, (unsigned long long)__double_as_longlong(r));
-        if (c) atomicAdd(&st->contra, (unsigned long long)c);
+        s_r[threadIdx.x >> 6] = r;
+        s_c[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NW; ++i) {
+            r = fmax(r, s_r[i]);
+            c += s_c[i];
+        }
+        const int slot = int(blockIdx.x % kRedSlots) * kRedStride;
+        if (r > 0.0) atomicMax(&st->rpart[slot], (unsigned long long)__double_as_longlong(r));
+        if (c) atomicAdd(&st->cpart[slot], (unsigned long long)c);
     }
 }
 
@@ -46,7 +62,7 @@ __global__ __launch_bounds__(256) void k_fac_rec(DevGraph<typename P::S, typenam
     const GPtr<const FacRec> R(recs);
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         factor_rec<P, DAMP>(g, R.ld_stream(i), acc);
-    flush_acc(acc, st);
+    flush_acc<256>(acc, st);
 }
 
 template <class P, bool ALL, bool DAMP>
@@ -58,7 +74,7 @@ __global__ __launch_bounds__(256) void k_fac_wave(DevGraph<typename P::S, typena
     const int waves = gridDim.x * (blockDim.x >> 6);
     for (int32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < count; i += waves)
         factor_wave<P, ALL, DAMP>(g, list[i], lane, level, acc);
-    flush_acc(acc, st);
+    flush_acc<256>(acc, st);
 }
 
 // One workgroup of NT threads per factor (1024 for float32; 512 for float64, whose factor code
@@ -71,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_fac_block(DevGraph<typename P::S, typena
     Acc acc = {0.0, 0u};
     for (int32_t i = blockIdx.x; i < count; i += gridDim.x)
         factor_team<P, NT, (kBlockMaxDeg - 1) / NT, ALL, DAMP>(g, list[i], threadIdx.x, level, acc, &lds);
-    flush_acc(acc, st);
+    flush_acc<NT>(acc, st);
 }
 
 template <class P>
@@ -105,9 +121,17 @@ __global__ __launch_bounds__(256) void k_var_wave(DevGraph<typename P::S, typena
         var_wave<P>(g, list[i], threadIdx.x & 63);
 }
 
+// Resets the residual slots (one 64-thread workgroup).
+__device__ __forceinline__ void clear_slots(RunState *st) {
+    for (int i = threadIdx.x; i < kRedSlots; i += blockDim.x) {
+        st->rpart[i * kRedStride] = 0ull;
+        st->cpart[i * kRedStride] = 0ull;
+    }
+}
+
 __global__ void k_run_init(RunState *st, int32_t max_iters, double tol) {
+    clear_slots(st);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->rbits = 0ull;
         st->contra = 0ull;
         st->iter = 0;
         st->done = max_iters <= 0 ? 1 : 0;
@@ -119,11 +143,24 @@ __global__ void k_run_init(RunState *st, int32_t max_iters, double tol) {
     }
 }
 
-// End of one iteration: publish the residual, decide whether to stop.
+static_assert(kRedSlots == 64, "k_finalize reduces the slots with one wavefront");
+
+// End of one iteration (one 64-thread workgroup): reduce and clear the residual slots, publish
+// the residual, decide whether to stop.
 __global__ void k_finalize(RunState *st) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || st->done) return;
-    double r = __longlong_as_double((long long)st->rbits);
-    st->rbits = 0ull;
+    if (st->done) return;
+    const int t = threadIdx.x;
+    double r = __longlong_as_double((long long)st->rpart[t * kRedStride]);
+    unsigned long long c = st->cpart[t * kRedStride];
+    st->rpart[t * kRedStride] = 0ull;
+    st->cpart[t * kRedStride] = 0ull;
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) {
+        r = fmax(r, __shfl_xor(r, k, 64));
+        c += __shfl_xor(c, k, 64);
+    }
+    if (t != 0) return;
+    st->contra += c;
     st->iter += 1;
     st->last_r = r;
     if (r < st->tol) {
@@ -478,6 +515,10 @@ static int grid_for(int64_t items, int per_block) {
     return int(std::max<int64_t>(1, std::min<int64_t>(b, 65535 * 8)));
 }
 
+// Grid of the factor kernels: at most 8 workgroups per compute unit (enough to reach their
+// occupancy); the workgroups loop over the rest, which bounds the residual atomics per launch.
+static int fac_grid(int64_t items, int per_block) { return std::min(grid_for(items, per_block), 256 * 8); }
+
 // parameters in the value domain of the precision: (p, 1-p) as log2 (FP32) or linear (FP64)
 template <class V>
 static Pair<V> param_pair(double p, bool logd) {
@@ -579,10 +620,10 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         int32_t o, n;
         o = pl.frec_off[L];
         n = pl.frec_off[L + 1] - o;
-        if (n) k_fac_rec<PP, DAMP><<<grid_for(n, 256), 256, 0, s>>>(dg, (const FacRec *)P.frec + o, n, g->st);
+        if (n) k_fac_rec<PP, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, (const FacRec *)P.frec + o, n, g->st);
         o = pl.fac_lvl_off[FB_WAVE][L];
         n = pl.fac_lvl_off[FB_WAVE][L + 1] - o;
-        if (n) k_fac_wave<PP, ALL, DAMP><<<grid_for(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
+        if (n) k_fac_wave<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
         o = pl.fac_lvl_off[FB_BLOCK][L];
         n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
         if (n)
@@ -651,7 +692,7 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
         HIPCHK(hipGetLastError());
         done_iters += K;
         if (done_iters >= max_iters) break;
-        HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(g->h_state, g->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (g->h_state->done) break;
     }
@@ -710,8 +751,8 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
 }
 
 __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int32_t step) {
+    clear_slots(st);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->rbits = 0ull;
         st->contra = 0ull;
         st->iter = 0;
         st->done = max_iters <= 0 ? 1 : 0;
@@ -829,7 +870,7 @@ float step_levels_finish(fastlbp_graph *g) {
 }
 
 void read_state(fastlbp_graph *g, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(g->h_state, g->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -1120,7 +1161,7 @@ int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping
         else
             run_dispatch<PolLin64>(g, max_iters, tol, damping, exec);
         HIPCHK(hipEventRecord(g->L.ev1, s));
-        HIPCHK(hipMemcpyAsync(g->h_state, g->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(g->h_state, g->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g->L.ev0, g->L.ev1));
@@ -1179,7 +1220,7 @@ int fastlbp_run_batch(int32_t n, fastlbp_graph_t *graphs, int32_t max_iters, dou
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g0->L.ev0, g0->L.ev1));
         for (int32_t i = 0; i < n; ++i) {
-            HIPCHK(hipMemcpyAsync(graphs[i]->h_state, graphs[i]->st, sizeof(RunState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(graphs[i]->h_state, graphs[i]->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             fastlbp_run_stats st;
             fill_stats(graphs[i], FASTLBP_EXEC_PERSISTENT, ms, st);
