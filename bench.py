@@ -39,6 +39,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
+# Measured HBM traffic of one k_persistent launch in the default configuration (256 queries, 8
+# iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
+# (profiles/k_persistent_smartfl_200k_batch256.md). Valid only for the kernel sources it was taken
+# with: any change to them makes the reported traffic null until it is measured again.
+TRAFFIC_DEFAULT = {"sources_sha256": "3f90e89278e46dec968b9e0b8fe1a7e50bee3ca22336475f47c81e38eb1f9873",
+                   "bytes_per_launch": 80803996138.6, "raw_bytes_per_launch": 51457663445.0,
+                   "queries": 256, "step_iters": 8}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2509_22337_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print("#", *a, file=sys.stderr, flush=True)
@@ -198,6 +217,53 @@ def serving_mix(F, W, args):
     return out
 
 
+def bingo_flooding(F, W, args):
+    """One BINGO-shaped graph (2M tuples, 4M rules, 19M edges), flooding, FP32 messages, on the
+    LEVELS executor: per iteration one launch per degree bucket and phase. A step is one run of
+    --max-iters (default 100) iterations; FP64 runs the same graph for the plain comparison."""
+    import torch
+    w = W.config("C3", seed=args.seed)
+    iters = args.max_iters or 100
+    log(f"workload bingo: V={w.num_vars} F={w.num_factors} E={w.num_edges} (non-prior {w.nonprior_edges()})")
+    res = {}
+    for prec in ("fp32", "fp64"):
+        g = F.Graph.from_workload(w, precision=prec, executor="levels")
+        steps = args.steps if prec == "fp32" else 1
+        for s in range(args.warmup + steps):
+            if s == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dev_ms, upd, alg = 0.0, 0, 0.0
+            g.messages_reset()
+            st = g.run(iters, 0.0, 0.0)
+            if s >= args.warmup:
+                dev_ms += st["device_ms"]
+                upd += st["message_updates"]
+                alg += st["algorithmic_bytes_per_iter"] * st["iterations"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        g.close()
+        res[prec] = dict(wall_s=wall, dev_ms=dev_ms, updates=upd, alg=alg, iters=st["iterations"], steps=steps)
+        log(f"bingo {prec}: {wall * 1e3 / steps:.1f} ms/run, {upd / wall / 1e9:.2f} G updates/s, "
+            f"{dev_ms * 1e3 / (steps * st['iterations']):.1f} us/iteration")
+    r = res["fp32"]
+    achieved = r["alg"] / (r["dev_ms"] / 1e3) / 1e9
+    return {
+        "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
+        "value": round(r["updates"] / r["wall_s"], 1), "unit": "message updates/s", "n_gpus": 1,
+        "steps": r["steps"], "warmup": args.warmup, "ms_per_step": round(r["wall_s"] * 1e3 / r["steps"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bingo_2M_tuples_4M_rules_19M_edges_flooding", "seed": args.seed,
+                   "num_vars": w.num_vars, "num_edges": w.num_edges, "iterations": iters, "executor": "levels"},
+        "us_per_iteration": round(r["dev_ms"] * 1e3 / (r["steps"] * r["iters"]), 2),
+        "plain_fp64": {"mups": round(res["fp64"]["updates"] / res["fp64"]["wall_s"], 1),
+                       "us_per_iteration": round(res["fp64"]["dev_ms"] * 1e3 / res["fp64"]["iters"], 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "one iteration of the LEVELS executor (all kernels)"},
+    }
+
+
 def cpu_baseline(w, budget_s: float):
     """The oracle (single thread) on a bounded sample: as many full iterations of the same graph,
     schedule and evidence as fit in about `budget_s` seconds."""
@@ -223,7 +289,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=64, help="queries per batched step")
+    ap.add_argument("--batch", type=int, default=256, help="queries per batched step")
     ap.add_argument("--step-iters", type=int, default=8, help="iterations per server launch")
     ap.add_argument("--fp64-queries", type=int, default=3)
     ap.add_argument("--max-iters", type=int, default=None, help="override the workload's 500")
@@ -231,9 +297,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
-    ap.add_argument("--workload", choices=["smartfl", "serving"], default="smartfl",
+    ap.add_argument("--workload", choices=["smartfl", "serving", "bingo"], default="smartfl",
                     help="smartfl: batched queries of the 200k-variable SmartFL-shaped graph; serving: the "
-                         "512-graph Poisson serving mix with warm re-queries")
+                         "512-graph Poisson serving mix with warm re-queries; bingo: one 19M-edge "
+                         "BINGO-shaped graph, flooding, 100 iterations (wide-level kernels)")
     ap.add_argument("--queries", type=int, default=512, help="graphs in the serving mix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (reference for HBM byte counters)")
@@ -259,6 +326,9 @@ def main():
     from paper_2509_22337_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     F.load()
+    if args.workload == "bingo":
+        print(json.dumps(bingo_flooding(F, W, args)), flush=True)
+        return
     if args.workload == "serving":
         rs = serving_mix(F, W, args)
         kernel_s = rs["kernel_ms"] / 1e3
@@ -313,8 +383,16 @@ def main():
     }
     kernel_s = rb["kernel_ms"] / 1e3
     achieved = rb["alg_bytes"] / kernel_s / 1e9
+    T = TRAFFIC_DEFAULT
+    traffic = None
+    if (args.batch == T["queries"] and args.step_iters == T["step_iters"] and args.seed == 0 and not args.max_iters
+            and kernel_sources_sha256() == T["sources_sha256"]):
+        traffic = T["bytes_per_launch"]
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_persistent<PolLog32>",
+                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                       "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-"
+                                       "calibrated); null when the kernel sources or launch shape differ from "
+                                       "the profiled ones", "kernel": "k_persistent<PolLog32>",
                        "launches": rb["launches"], "avg_launch_ms": round(rb["kernel_ms"] / max(1, rb["launches"]), 4),
                        "algorithmic_bytes": rb["alg_bytes"]}
     if not args.batched_only:

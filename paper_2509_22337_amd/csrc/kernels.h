@@ -564,7 +564,9 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
 // issues all of a task's dynamic loads (messages, beliefs) at once. Records of a level are sorted
 // by degree and every degree group is padded to a multiple of 64, so the 64 records a wavefront
 // takes share one degree: the degree switch below is then uniform and each case loads exactly its
-// degree's operands.
+// degree's operands. (Without the padding, a wavefront straddling two degrees runs both cases one
+// after the other, which doubles its chain of dependent loads; on narrow levels the slowest
+// wavefront sets the level's time.)
 // ------------------------------------------------------------------------------------------------
 
 // One factor of degree D from values in registers: lo[k] the old message of edge b + k, vf[k] its

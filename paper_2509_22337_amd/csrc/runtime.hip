@@ -639,10 +639,14 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
     k_finalize<<<1, 64, 0, s>>>(g->st);
 }
 
-// Workgroup size of the persistent executor: 1024 threads for float32 plans without wavefront or
-// workgroup factors, else 512 (float64 factor code and the team paths need more than the 128
-// registers a 1024-thread workgroup allows; only the 1024-thread float32 thread-task variant fits).
-static int persistent_threads(int precision, bool teams) { return (precision == FASTLBP_FP32 && !teams) ? 1024 : 512; }
+// Workgroup size of the persistent executor. 512 threads in general (float64 factor code and the
+// team paths need more than the 128 registers a 1024-thread workgroup allows). A launch of at most
+// as many runs as compute units, all float32 with thread tasks only, takes 1024 threads: each run
+// has a compute unit to itself, and levels of up to 1024 tasks finish in one pass. With more runs,
+// two 512-thread workgroups share a compute unit, so twice as many runs are in flight.
+static int persistent_threads(int precision, bool teams, int runs) {
+    return (precision == FASTLBP_FP32 && !teams && runs <= 256) ? 1024 : 512;
+}
 
 static int choose_executor(const fastlbp_graph *g) {
     int ex = g->opts.executor;
@@ -719,7 +723,7 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     }
     HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, lc.stream));
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
-    int nt = persistent_threads(gs[0]->precision(), teams);
+    int nt = persistent_threads(gs[0]->precision(), teams, n);
     hipStream_t s = lc.stream;
     // LDS for the record offsets of the deepest schedule in the launch, up to 8192 levels (64 KiB)
     int32_t max_levels = 0;
