@@ -47,8 +47,8 @@ void clear_error();
 
 // The server drives runs in steps: step_begin resets a handle's run state (iteration 0) for a
 // run of max_iters; step_run advances n handles by up to `step` iterations in one persistent
-// launch (one workgroup per handle) and waits for it; read_state copies a handle's run state
-// to its pinned host mirror (graph_host_state).
+// launch (one workgroup per handle), waits for it and refreshes their pinned host state mirrors
+// (graph_host_state); read_state refreshes one handle's mirror (runs stepped elsewhere).
 Launcher *launcher_create(int device, hipStream_t s, const Alloc &a);
 void launcher_destroy(Launcher *l);
 hipStream_t launcher_stream(Launcher *l);

@@ -196,6 +196,8 @@ struct RunDesc {
     DevGraph<typename P::S, typename P::V> g;
     DevPlan plan;
     GPtr<RunState> st;
+    GPtr<int32_t> status;  // receives a copy of the run's state header when the launch ends
+    int32_t step;          // > 0: this launch stops the run after `step` more iterations
 };
 
 // One workgroup of NT threads runs every level and iteration of one run, with workgroup barriers
@@ -234,7 +236,10 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     auto voff = [&](int32_t L) { return off_lds ? s_off[lds_levels + 1 + L] : (int32_t)plan.vrec_off[L]; };
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
-    if (tid == 0) s_done = st->done || st->iter >= st->step_end;
+    if (tid == 0) {
+        if (D.step > 0) st->step_end = st->iter + D.step;
+        s_done = st->done || st->iter >= st->step_end;
+    }
     __syncthreads();
     FacRec fr = {};
     if (NL > 0 && foff(0) + tid < foff(1)) fr = frec.ld_stream(foff(0) + tid);
@@ -307,6 +312,11 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
             s_done = st->done || st->iter >= st->step_end;
         }
         __syncthreads();
+    }
+    // state header for the host, gathered with the other runs' into one array
+    if (tid == 0) {
+        const __attribute__((address_space(1))) int32_t *src = (const __attribute__((address_space(1))) int32_t *)st.get();
+        for (int k = 0; k < int(kRunStateHeader / 4); ++k) D.status[k] = src[k];
     }
 }
 
@@ -402,6 +412,8 @@ struct Launcher {
     void *desc = nullptr;
     size_t desc_cap = 0;
     std::vector<unsigned char> hdesc;
+    unsigned char *hstatus = nullptr;  // pinned copy of the runs' state headers after a launch
+    size_t hstatus_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t k0 = nullptr, k1 = nullptr;  // around the last persistent kernel
     float last_kernel_ms = 0.f;
@@ -426,8 +438,19 @@ struct Launcher {
         }
         return desc;
     }
+    unsigned char *status_host(size_t bytes) {
+        if (bytes > hstatus_cap) {
+            if (hstatus) (void)hipHostFree(hstatus);
+            hstatus = nullptr;
+            hstatus_cap = 0;
+            HIPCHK(hipHostMalloc((void **)&hstatus, bytes, hipHostMallocDefault));
+            hstatus_cap = bytes;
+        }
+        return hstatus;
+    }
     ~Launcher() {
         if (stream) (void)hipStreamSynchronize(stream);
+        if (hstatus) (void)hipHostFree(hstatus);
         pool.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -455,6 +478,8 @@ struct fastlbp_graph {
     double *marg = nullptr;
     Launcher L;
     RunState *h_state = nullptr;  // pinned copy
+    void *ev_buf = nullptr;       // staging for evidence updates (indices + potentials)
+    size_t ev_cap = 0;
     // captured iterations of the LEVELS executor
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -478,6 +503,7 @@ struct fastlbp_graph {
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         drop_graph();
         state.release();
+        alloc.put(ev_buf);
         if (h_state) (void)hipHostFree(h_state);
     }
     template <class PP>
@@ -568,17 +594,58 @@ static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, h
     return P;
 }
 
-static void upload_phi(fastlbp_graph *g) {
-    std::vector<Belief> phi;
-    const HostGraph &hg = g->hg();
-    phi.resize(hg.V);
-    for (int32_t v = 0; v < hg.V; ++v) {
-        Belief b;
-        b.fin = hg.prior_fin[v];
-        b.npos = hg.prior_pos[v] + (g->evidence[v] == 1 ? 1 : 0);
-        b.nneg = hg.prior_neg[v] + (g->evidence[v] == 0 ? 1 : 0);
-        phi[v] = b;
+__global__ void k_phi_scatter(Belief *phi, const int32_t *idx, const Belief *val, int32_t n) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) phi[idx[i]] = val[i];
+}
+
+static Belief phi_of(const fastlbp_graph *g, int32_t v);
+static void upload_phi(fastlbp_graph *g);
+
+// Refreshes phi for the variables in `changed` (any order, repeats allowed): a small scatter when
+// few change, the whole array otherwise. Evidence updates thus cost O(clamps), not O(V).
+static void update_phi(fastlbp_graph *g, std::vector<int32_t> &changed) {
+    std::sort(changed.begin(), changed.end());
+    changed.erase(std::unique(changed.begin(), changed.end()), changed.end());
+    const int32_t n = int32_t(changed.size());
+    if (n == 0) return;
+    if (int64_t(n) * 16 > g->hg().V) {
+        upload_phi(g);
+        return;
     }
+    const size_t ib = (sizeof(int32_t) * size_t(n) + 15) & ~size_t(15);
+    const size_t bytes = ib + sizeof(Belief) * size_t(n);
+    if (bytes > g->ev_cap) {
+        g->alloc.put(g->ev_buf);
+        g->ev_buf = nullptr;
+        g->ev_cap = 0;
+        g->ev_buf = g->alloc.get(bytes);
+        if (!g->ev_buf) throw OomError{};
+        g->ev_cap = bytes;
+    }
+    std::vector<unsigned char> host(bytes);
+    std::memcpy(host.data(), changed.data(), sizeof(int32_t) * size_t(n));
+    Belief *hv = (Belief *)(host.data() + ib);
+    for (int32_t i = 0; i < n; ++i) hv[i] = phi_of(g, changed[i]);
+    HIPCHK(hipMemcpyAsync(g->ev_buf, host.data(), bytes, hipMemcpyHostToDevice, g->L.stream));
+    k_phi_scatter<<<(n + 255) / 256, 256, 0, g->L.stream>>>(g->phi, (const int32_t *)g->ev_buf,
+                                                            (const Belief *)((unsigned char *)g->ev_buf + ib), n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(g->L.stream));  // `host` dies on return
+}
+
+static Belief phi_of(const fastlbp_graph *g, int32_t v) {
+    const HostGraph &hg = g->hg();
+    Belief b;
+    b.fin = hg.prior_fin[v];
+    b.npos = hg.prior_pos[v] + (g->evidence[v] == 1 ? 1 : 0);
+    b.nneg = hg.prior_neg[v] + (g->evidence[v] == 0 ? 1 : 0);
+    return b;
+}
+
+static void upload_phi(fastlbp_graph *g) {
+    std::vector<Belief> phi(g->hg().V);
+    for (int32_t v = 0; v < g->hg().V; ++v) phi[v] = phi_of(g, v);
     if (phi.empty()) return;
     HIPCHK(hipMemcpyAsync(g->phi, phi.data(), sizeof(Belief) * phi.size(), hipMemcpyHostToDevice, g->L.stream));
     HIPCHK(hipStreamSynchronize(g->L.stream));
@@ -703,25 +770,33 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
 }
 
 // One persistent launch over n runs (one workgroup each) on `lc`'s stream. Every run advances
-// until it is done or its iteration count reaches its step_end.
+// until it is done or its iteration count reaches its step_end (with step > 0, first set to
+// step iterations past the current count). On return every run's host state header is current.
 template <class PP>
-static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping) {
+static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping,
+                              int32_t step = 0) {
     if (n <= 0) return;
     bool teams = false, damp = false;
     for (int i = 0; i < n; ++i) {
         teams = teams || gs[i]->P->teams();
         damp = damp || damping[i] > 0.0;
     }
-    size_t bytes = sizeof(RunDesc<PP>) * size_t(n);
+    const size_t dbytes = sizeof(RunDesc<PP>) * size_t(n);
+    const size_t sbytes = kRunStateHeader * size_t(n);
+    const size_t bytes = dbytes + sbytes;
     void *d = lc.descs(bytes);
-    lc.hdesc.resize(bytes);
+    int32_t *dstatus = (int32_t *)((unsigned char *)d + dbytes);
+    lc.hdesc.resize(dbytes);
     RunDesc<PP> *h = (RunDesc<PP> *)lc.hdesc.data();
     for (int i = 0; i < n; ++i) {
         h[i].g = gs[i]->view<PP>(damping[i]);
         h[i].plan = gs[i]->P->view();
         h[i].st = GPtr<RunState>(gs[i]->st);
+        h[i].status = GPtr<int32_t>(dstatus + i * int(kRunStateHeader / 4));
+        h[i].step = step;
     }
-    HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, lc.stream));
+    unsigned char *hs = lc.status_host(sbytes);
+    HIPCHK(hipMemcpyAsync(d, h, dbytes, hipMemcpyHostToDevice, lc.stream));
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
     int nt = persistent_threads(gs[0]->precision(), teams, n);
     hipStream_t s = lc.stream;
@@ -749,9 +824,11 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
 #undef FASTLBP_LAUNCH
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(lc.k1, s));
-    // the host staging buffer may be rewritten by the next call
+    HIPCHK(hipMemcpyAsync(hs, dstatus, sbytes, hipMemcpyDeviceToHost, s));
+    // (the descriptor staging buffer may be rewritten by the next call only after this)
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipEventElapsedTime(&lc.last_kernel_ms, lc.k0, lc.k1));
+    for (int i = 0; i < n; ++i) std::memcpy(gs[i]->h_state, hs + kRunStateHeader * size_t(i), kRunStateHeader);
 }
 
 __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int32_t step) {
@@ -766,10 +843,6 @@ __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int
         st->tol = tol;
         st->step_end = step;
     }
-}
-
-__global__ void k_step_advance(RunState *st, int32_t step) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->step_end = st->iter + step;
 }
 
 template <class PP, bool ALL, bool DAMP>
@@ -821,12 +894,10 @@ void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step) {
 }
 
 void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
-    for (int i = 0; i < n; ++i) k_step_advance<<<1, 64, 0, lc.stream>>>(gs[i]->st, step);
-    HIPCHK(hipGetLastError());
     if (gs[0]->precision() == FASTLBP_FP32)
-        launch_persistent<PolLog32>(lc, n, gs, damping);
+        launch_persistent<PolLog32>(lc, n, gs, damping, step);
     else
-        launch_persistent<PolLin64>(lc, n, gs, damping);
+        launch_persistent<PolLin64>(lc, n, gs, damping, step);
 }
 
 // A server step of a run on the LEVELS executor: beliefs rebuilt (the evidence may be new), then
@@ -898,8 +969,20 @@ int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t 
             set_error("evidence entry " + std::to_string(i) + " out of range");
             return FASTLBP_E_INVALID_ARG;
         }
-    for (int32_t i = 0; i < n; ++i) g->evidence[vars[i]] = values[i];
-    upload_phi(g);
+    std::vector<int32_t> changed;
+    std::vector<int8_t> before;
+    for (int32_t i = 0; i < n; ++i)
+        if (g->evidence[vars[i]] != values[i]) {
+            changed.push_back(vars[i]);
+            before.push_back(g->evidence[vars[i]]);
+            g->evidence[vars[i]] = values[i];
+        }
+    try {
+        update_phi(g, changed);
+    } catch (...) {  // leave the handle's evidence as it was
+        for (size_t i = changed.size(); i-- > 0;) g->evidence[changed[i]] = before[i];
+        throw;
+    }
     return FASTLBP_OK;
 }
 
@@ -1119,6 +1202,9 @@ int fastlbp_evidence_set(fastlbp_graph_t g, int32_t n, const int32_t *vars, cons
     }
     try {
         return set_evidence(g, n, vars, values);
+    } catch (OomError &) {
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
     } catch (DeviceError &e) {
         return device_error(e);
     }
@@ -1130,10 +1216,21 @@ int fastlbp_evidence_clear(fastlbp_graph_t g) {
         set_error("graph is NULL");
         return FASTLBP_E_INVALID_ARG;
     }
-    std::fill(g->evidence.begin(), g->evidence.end(), int8_t(-1));
+    std::vector<int8_t> saved = g->evidence;
     try {
-        upload_phi(g);
+        std::vector<int32_t> changed;
+        for (int32_t v = 0; v < int32_t(g->evidence.size()); ++v)
+            if (g->evidence[v] != -1) {
+                g->evidence[v] = -1;
+                changed.push_back(v);
+            }
+        update_phi(g, changed);
+    } catch (OomError &) {
+        g->evidence = saved;
+        set_error("device allocation failed");
+        return FASTLBP_E_OOM;
     } catch (DeviceError &e) {
+        g->evidence = saved;
         return device_error(e);
     }
     return FASTLBP_OK;
@@ -1223,9 +1320,7 @@ int fastlbp_run_batch(int32_t n, fastlbp_graph_t *graphs, int32_t max_iters, dou
         HIPCHK(hipStreamSynchronize(s));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g0->L.ev0, g0->L.ev1));
-        for (int32_t i = 0; i < n; ++i) {
-            HIPCHK(hipMemcpyAsync(graphs[i]->h_state, graphs[i]->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < n; ++i) {  // host state headers were refreshed by the launch
             fastlbp_run_stats st;
             fill_stats(graphs[i], FASTLBP_EXEC_PERSISTENT, ms, st);
             if (stats) stats[i] = st;

@@ -100,6 +100,11 @@ void fastlbp_server::loop() {
                         continue;
                     }
                     step_begin(r->g, r->max_iters, r->tol, 0);
+                } catch (OomError &) {
+                    r->status = FASTLBP_E_OOM;
+                    r->error = "device allocation failed";
+                    cv_done.notify_all();
+                    continue;
                 } catch (DeviceError &e) {
                     r->status = FASTLBP_E_DEVICE;
                     r->error = e.msg;
@@ -144,7 +149,8 @@ void fastlbp_server::loop() {
                 dev_ms = launcher_kernel_ms(launcher);
             }
             for (auto *g : wide) dev_ms = std::max(dev_ms, step_levels_finish(g));
-            for (size_t i = 0; i < gs.size(); ++i) read_state(gs[i], launcher_stream(launcher));
+            // the persistent launch refreshed the narrow runs' host state; the wide ones are read
+            for (auto *g : wide) read_state(g, launcher_stream(launcher));
         } catch (DeviceError &e) {
             err = e.msg;
             for (auto *g : wide) {

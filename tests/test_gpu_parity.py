@@ -220,6 +220,40 @@ def test_bucket_boundary_degrees(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_evidence_update_paths(precision):
+    # few changed clamps are scattered into the device potentials, many are re-uploaded whole,
+    # clearing resets the clamped ones: any sequence must leave the same potentials as setting
+    # the final evidence on a fresh handle
+    w = W.random_loopy(12, num_vars=400, num_factors=500, max_arity=6)
+    rng = np.random.default_rng(8)
+    h1 = F.Graph.from_workload(w, precision=precision)
+    h1.evidence_clear()
+    small = rng.choice(w.num_vars, size=5, replace=False).astype(np.int32)
+    h1.evidence_set(small, rng.integers(0, 2, 5).astype(np.int8))  # scatter
+    big = rng.choice(w.num_vars, size=200, replace=False).astype(np.int32)
+    h1.evidence_set(big, rng.integers(0, 2, 200).astype(np.int8))  # whole array
+    h1.evidence_set(big[:3], np.full(3, -1, np.int8))  # release a few
+    h1.evidence_clear()
+    final = np.full(w.num_vars, -1, np.int8)
+    last = rng.choice(w.num_vars, size=7, replace=False).astype(np.int32)
+    vals = rng.integers(0, 2, 7).astype(np.int8)
+    h1.evidence_set(np.concatenate([last, last[:2]]), np.concatenate([1 - vals[:2], vals[2:], vals[:2]]))
+    final[last] = vals
+    h1.messages_reset()
+    st1 = h1.run(10, 0.0, 0.0)
+    m1 = h1.marginals()
+    h2 = F.Graph.from_workload(w, precision=precision)
+    h2.evidence_array(final)
+    h2.messages_reset()
+    st2 = h2.run(10, 0.0, 0.0)
+    m2 = h2.marginals()
+    h1.close()
+    h2.close()
+    assert np.array_equal(m1, m2)
+    assert st1["contradictions"] == st2["contradictions"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_one_step_parity(precision):
     # same start state (including exact 0/1 messages), one iteration of a ranked schedule
     w = W.random_loopy(7, num_vars=60, num_factors=90, max_arity=9)
