@@ -377,7 +377,8 @@ def main():
                    "num_vars": w.num_vars, "num_edges": w.num_edges, "levels": 998, "max_iters": w.max_iters,
                    "tol": w.tol, "queries_per_step": args.batch, "step_iters": args.step_iters,
                    "executor": "persistent, one workgroup per query"},
-        "batched_fp32": {"mups": round(mups_b, 1), "p50_ms": pct(rb["lat_ms"], 50), "p99_ms": pct(rb["lat_ms"], 99),
+        "batched_fp32": {"mups": round(mups_b, 1), "device_mups": round(rb["updates"] / (rb["kernel_ms"] / 1e3), 1),
+                         "p50_ms": pct(rb["lat_ms"], 50), "p99_ms": pct(rb["lat_ms"], 99),
                          "queries": len(rb["lat_ms"]), "iterations_p50": int(np.median(rb["iters"])),
                          "iterations_max": int(max(rb["iters"]))},
     }
