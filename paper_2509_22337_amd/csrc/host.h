@@ -59,6 +59,11 @@ struct HostPlan {
     // degree group padded to a multiple of 64 records; frec_off / vrec_off delimit the levels
     std::vector<int32_t> frec, vrec;
     std::vector<int32_t> frec_off, vrec_off;
+    // levels whose new messages the persistent executor stages in LDS: flag per level, variable
+    // tasks with staging slots (8 int32 each, in vrec's order), most slots of a staged level
+    std::vector<int32_t> level_lds;
+    std::vector<int32_t> prec;
+    int32_t stage_slots = 0;
     double bytes_per_iter = 0.0;   // algorithmic bytes of one iteration
     int64_t updates_per_iter = 0;  // non-PRIOR edges written per iteration
 

@@ -389,6 +389,47 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         }
         vrec_off.push_back(int32_t(vrec.size() / 8));
     }
+    // staging in LDS: a level qualifies when all of its written edges come from thread-bucket
+    // factors, its variables have at most kStagedEdges written edges each and none takes the
+    // wavefront path, and its written edges fit kMaxStageSlots
+    level_lds.assign(exec_levels, 0);
+    prec.assign(vrec.size(), 0);
+    stage_slots = 0;
+    std::vector<int32_t> edge_slot(g.E, -1);
+    for (int32_t L = 0; L < exec_levels; ++L) {
+        bool ok = fac_lvl_off[FB_WAVE][L + 1] == fac_lvl_off[FB_WAVE][L] &&
+                  fac_lvl_off[FB_BLOCK][L + 1] == fac_lvl_off[FB_BLOCK][L] &&
+                  var_lvl_off[VB_WAVE][L + 1] == var_lvl_off[VB_WAVE][L];
+        int32_t slots = 0;
+        for (int32_t i = frec_off[L]; i < frec_off[L + 1]; ++i) {
+            int32_t *r = &frec[size_t(i) * 12];
+            const int32_t b = r[0], d = r[1] & 0xff;
+            const unsigned active = (unsigned)(r[1] >> 16) & 0xffu;
+            r[11] = slots;
+            for (int k = 0; k < d; ++k)
+                if ((active >> k) & 1u) edge_slot[b + k] = slots++;
+        }
+        ok = ok && slots <= kMaxStageSlots;
+        for (int32_t i = vrec_off[L]; ok && i < vrec_off[L + 1]; ++i) {
+            const int32_t *r = &vrec[size_t(i) * 8];
+            const int32_t v = r[0];
+            int32_t *q = &prec[size_t(i) * 8];
+            q[0] = v;
+            int32_t n = 0;
+            for (int32_t p = g.var_off[v]; p < g.var_off[v + 1]; ++p) {
+                const int32_t e = g.var_edge[p];
+                if (edge_exec_level[e] != L) continue;
+                if (n == kStagedEdges || edge_slot[e] < 0) {
+                    ok = false;
+                    break;
+                }
+                q[2 + n++] = edge_slot[e];
+            }
+            q[1] = n | (r[2] & (1 << 30));  // keeps the padding flag
+        }
+        level_lds[L] = ok ? 1 : 0;
+        if (ok) stage_slots = std::max(stage_slots, slots);
+    }
 }
 
 }  // namespace fastlbp

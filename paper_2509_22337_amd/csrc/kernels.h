@@ -572,11 +572,24 @@ __device__ __forceinline__ void var_wave(const DevGraph<typename P::S, typename 
 // One factor of degree D from values in registers: lo[k] the old message of edge b + k, vf[k] its
 // variable-to-factor message, nl[k] whether that is the null message. Bit k of `active` selects
 // the edges the level writes.
+// Puts the new and the old message of active edge k into the level's staging slots (when given).
+template <class P>
+__device__ __forceinline__ void stage_slot(typename P::S *slots, int32_t slot0, unsigned active, int k,
+                                           typename P::S nw, typename P::S old) {
+    if (slots) {
+        const int32_t i = slot0 + __builtin_popcount(active & ((1u << k) - 1u));
+        slots[2 * i] = nw;
+        slots[2 * i + 1] = old;
+    }
+}
+
 template <class P, bool DAMP, int D>
 __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int32_t b,
                                              unsigned active, const Pair<typename P::V> &fp,
                                              const typename P::S (&lo)[D], const typename P::S (&vf)[D],
-                                             const bool (&nl)[D], const Pair<typename P::V> (&ep)[D], Acc &acc) {
+                                             const bool (&nl)[D], const Pair<typename P::V> (&ep)[D], Acc &acc,
+                                             typename P::S *slots, int32_t slot0) {
+    using S = typename P::S;
     using V = typename P::V;
     if constexpr (D == 2) {
         if (type == T_NOT) {
@@ -585,7 +598,9 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
                 if (!((active >> k) & 1u)) continue;
                 V m0, m1;
                 P::leaf(-vf[1 - k], m0, m1);
-                store_msg<P, DAMP>(g, b + k, lo[k], m0, m1, nl[1 - k], acc);
+                const S l = finish_msg<P, DAMP>(g, lo[k], m0, m1, nl[1 - k], acc);
+                g.msg[b + k] = l;
+                stage_slot<P>(slots, slot0, active, k, l, lo[k]);
             }
             return;
         }
@@ -614,7 +629,9 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
     if ((active >> n) & 1u) {
         V o0, o1;
         head_msg<P>(type, tot, fp, o0, o1);
-        g.msg[b + n] = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
+        const S l = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
+        g.msg[b + n] = l;
+        stage_slot<P>(slots, slot0, active, n, l, lo[n]);
     }
     HF<V> sx[n];
     HF<V> run = identity<P>();
@@ -631,7 +648,9 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
             V o0, o1;
             input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
             int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
-            g.msg[b + k] = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
+            const S l = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
+            g.msg[b + k] = l;
+            stage_slot<P>(slots, slot0, active, k, l, lo[k]);
         }
         run = combine<P>(run, lf[k]);
     }
@@ -641,7 +660,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
 template <class P, bool DAMP, int D>
 __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
                                                      int type, int32_t fac, unsigned active, const int32_t *u,
-                                                     Acc &acc) {
+                                                     Acc &acc, typename P::S *slots, int32_t slot0) {
     using S = typename P::S;
     using V = typename P::V;
     S lo[D];
@@ -664,21 +683,24 @@ __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::
     bool nl[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) vf[k] = v2f<P>(B[k], lo[k], nl[k]);
-    factor_local<P, DAMP, D>(g, type, b, active, fp, lo, vf, nl, ep, acc);
+    factor_local<P, DAMP, D>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
 }
 
+// `slots`: the level's LDS staging area (persistent executor, staged levels), else nullptr.
 template <class P, bool DAMP>
-__device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc) {
+__device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc,
+                                           typename P::S *slots = nullptr) {
     const int d = r.meta & 0xff, type = (r.meta >> 8) & 0xff;
     const unsigned active = (unsigned)(r.meta >> 16) & 0xffu;
+    const int32_t slot0 = r.u[8];
     switch (d) {
-    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc); break;
-    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc); break;
+    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
     default: break;
     }
 }
@@ -713,6 +735,36 @@ __device__ __forceinline__ void var_rec(const DevGraph<typename P::S, typename P
     case 4: var_rec_c<P, 4>(g, r, cnt, pad); break;
     default: var_rec_c<P, kVarRecEdges>(g, r, cnt, pad); break;
     }
+}
+
+template <class P>
+__device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
+    using S = typename P::S;
+    const S inf = (S)__builtin_huge_val();
+    if (l == inf)
+        B.npos--;
+    else if (l == -inf)
+        B.nneg--;
+    else
+        B.fin -= (double)l;
+}
+
+// Variable task of a staged level: B (its belief before the level, already loaded) plus, for each
+// message the level wrote, new minus old, read from the staging slots. The counts of infinite
+// terms stay exact; the finite part is updated in float64 (the whole belief is rebuilt from the
+// messages at the start of every launch).
+template <class P>
+__device__ __forceinline__ void var_staged(const DevGraph<typename P::S, typename P::V> &g, const VarRecP &r,
+                                           Belief B, const typename P::S *slots) {
+    const int n = r.n & 0xffff;
+    const bool pad = (r.n >> 30) & 1;
+#pragma unroll
+    for (int j = 0; j < kStagedEdges; ++j)
+        if (j < n) {
+            belief_sub<P>(B, slots[2 * r.s[j] + 1]);
+            belief_add<P>(B, slots[2 * r.s[j]]);
+        }
+    if (!pad) g.bel.st(r.v, B);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -139,12 +139,24 @@ struct alignas(16) FacRec {
     int32_t b;     // first edge
     int32_t meta;  // degree | type << 8 | (edges the level writes, bit k = edge b + k) << 16
     int32_t fac;   // factor id (for its parameters)
-    int32_t u[9];  // variable of edge b + k, k < degree (<= 8)
+    int32_t u[9];  // variable of edge b + k, k < degree (<= 8); u[8]: first staging slot of the
+                   // record's written edges (persistent executor, levels staged in LDS)
 };
 
 struct alignas(16) VarRec {
     int32_t v, start, cnt;  // variable, first position in var_edge, degree | (padding record) << 30
     int32_t e[5];           // its first edges (the rest from var_edge)
+};
+
+// Variable task of a level staged in LDS (persistent executor): the variable, how many of its
+// messages the level writes (| padding record << 30) and their staging slots. Its belief is
+// updated from the value before the level plus (new - old) of those messages.
+constexpr int kStagedEdges = 6;
+constexpr int kMaxStageSlots = 2048;  // written edges of a level that may be staged in LDS
+struct alignas(16) VarRecP {
+    int32_t v;
+    int32_t n;
+    int32_t s[kStagedEdges];
 };
 
 struct DevPlan {
@@ -162,6 +174,11 @@ struct DevPlan {
     GPtr<const int32_t> frec_off;  // [num_levels+1]
     GPtr<const VarRec> vrec;
     GPtr<const int32_t> vrec_off;  // [num_levels+1]
+    // levels staged in LDS (persistent executor): per level 1 if its variable phase reads the
+    // level's new messages from LDS (then prec holds its variable tasks, in vrec's order)
+    GPtr<const VarRecP> prec;
+    GPtr<const int32_t> level_lds;  // [num_levels]
+    int32_t stage_slots;            // most slots any staged level uses (0: none staged)
 };
 
 }  // namespace fastlbp

@@ -208,14 +208,19 @@ struct RunDesc {
 // (plans with factors of degree > 8). A launch returns when the run is done or its iteration
 // count reaches st->step_end, so a caller can advance many runs in steps.
 template <class P, bool DAMP, bool TEAMS, int NT>
-__global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int32_t lds_levels) {
+__global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int32_t lds_levels, int32_t stage_cap) {
+    using S = typename P::S;
     using V = typename P::V;
     constexpr int NW = NT / 64;
     __shared__ TeamLds<V> lds;
     __shared__ double red_r[NW];
     __shared__ unsigned int red_c[NW];
     __shared__ int s_done;
-    extern __shared__ int32_t s_off[];  // factor then variable record offsets, when they fit
+    // dynamic LDS: staging slots (new, old message pairs of a staged level's written edges), then
+    // the per-level factor record offsets, variable record offsets and staging flags
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    S *const s_slot = (S *)s_dyn;
+    int32_t *const s_off = (int32_t *)(s_dyn + sizeof(S) * 2 * size_t(stage_cap));
     const RunDesc<P> &D = descs[blockIdx.x];
     const DevGraph<typename P::S, typename P::V> g = D.g;
     const DevPlan plan = D.plan;
@@ -223,17 +228,24 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const GPtr<const FacRec> frec = plan.frec;
     const GPtr<const VarRec> vrec = plan.vrec;
+    const GPtr<const VarRecP> prec = plan.prec;
     const int32_t NL = plan.num_levels;
-    // per-level record offsets: staged once in LDS so that a level does not start with a round
+    // staged levels need the launch's slot area to hold this plan's largest staged level
+    const bool staging = plan.stage_slots > 0 && plan.stage_slots <= stage_cap;
+    // per-level offsets and flags: staged once in LDS so that a level does not start with a round
     // trip to memory (schedules deeper than the launch's LDS allowance read them from memory)
     const bool off_lds = NL <= lds_levels;
     if (off_lds)
         for (int32_t i = tid; i <= NL; i += NT) {
             s_off[i] = plan.frec_off[i];
             s_off[lds_levels + 1 + i] = plan.vrec_off[i];
+            s_off[2 * (lds_levels + 1) + i] = (staging && i < NL) ? (int32_t)plan.level_lds[i] : 0;
         }
     auto foff = [&](int32_t L) { return off_lds ? s_off[L] : (int32_t)plan.frec_off[L]; };
     auto voff = [&](int32_t L) { return off_lds ? s_off[lds_levels + 1 + L] : (int32_t)plan.vrec_off[L]; };
+    auto staged = [&](int32_t L) {
+        return off_lds ? s_off[2 * (lds_levels + 1) + L] != 0 : (staging && plan.level_lds[L] != 0);
+    };
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
     if (tid == 0) {
@@ -241,17 +253,31 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
         s_done = st->done || st->iter >= st->step_end;
     }
     __syncthreads();
+    // records of level 0: the factor record, and the staged variable record when level 0 is staged
     FacRec fr = {};
+    VarRecP pr = {};
     if (NL > 0 && foff(0) + tid < foff(1)) fr = frec.ld_stream(foff(0) + tid);
+    if (NL > 0 && staged(0) && voff(0) + tid < voff(1)) pr = prec.ld_stream(voff(0) + tid);
     while (!s_done) {
         Acc acc = {0.0, 0u};
         for (int32_t L = 0; L < NL; ++L) {
             const int32_t f0 = foff(L), f1 = foff(L + 1);
             const int32_t v0 = voff(L), v1 = voff(L + 1);
+            const bool stg = staged(L);
+            // variable phase inputs, issued now: a staged level needs each variable's belief
+            // before the level; an unstaged one its record
             VarRec vr = {};
-            if (v0 + tid < v1) vr = vrec.ld_stream(v0 + tid);  // used by this level's variable phase
-            if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc);
-            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc);
+            Belief bold = {0.0, 0, 0};
+            const VarRecP pc = pr;
+            if (v0 + tid < v1) {
+                if (stg)
+                    bold = g.bel.ld(pc.v);
+                else
+                    vr = vrec.ld_stream(v0 + tid);
+            }
+            S *const slots = stg ? s_slot : nullptr;
+            if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots);
+            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots);
             if (TEAMS) {
                 const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
                 int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
@@ -263,21 +289,39 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
                 for (int32_t i = o0; i < o1; ++i)
                     factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, &lds);
             }
-            __syncthreads();
+            if (stg) {
+                // the variable phase reads only the staging slots and beliefs loaded before the
+                // level: wait for LDS, not for the messages' global stores
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            } else {
+                __syncthreads();
+            }
             {
-                // factor records of the next level (level 0 of the next iteration after the last)
+                // records of the next level (level 0 of the next iteration after the last)
                 const int32_t Ln = (L + 1 < NL) ? L + 1 : 0;
                 const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
                 fr = FacRec{};
                 if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
+                pr = VarRecP{};
+                const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
+                if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
             }
-            if (v0 + tid < v1) var_rec<P>(g, vr);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
-            {
+            if (stg) {
+                if (v0 + tid < v1) var_staged<P>(g, pc, bold, s_slot);
+                for (int32_t i = v0 + tid + NT; i < v1; i += NT) {
+                    const VarRecP q = prec.ld_stream(i);
+                    var_staged<P>(g, q, g.bel.ld(q.v), s_slot);
+                }
+            } else {
+                if (v0 + tid < v1) var_rec<P>(g, vr);
+                for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
                 const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
                 int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
                 for (int32_t i = o0 + w; i < o1; i += NW) var_wave<P>(g, lst[i], lane);
             }
+            // the next level reads these beliefs and messages from memory
             __syncthreads();
         }
         // end of iteration: block-wide residual and contradiction count
@@ -381,6 +425,7 @@ struct Plan {
     int32_t *fac_list[FB_COUNT] = {}, *fac_lvl_off[FB_COUNT] = {};
     int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
     int32_t *frec = nullptr, *vrec = nullptr, *frec_off = nullptr, *vrec_off = nullptr;
+    int32_t *prec = nullptr, *level_lds = nullptr;
     bool teams() const { return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty(); }
     DevPlan view() const {
         DevPlan p;
@@ -400,6 +445,9 @@ struct Plan {
         p.frec_off = frec_off;
         p.vrec = (const VarRec *)vrec;
         p.vrec_off = vrec_off;
+        p.prec = (const VarRecP *)prec;
+        p.level_lds = level_lds;
+        p.stage_slots = hp.stage_slots;
         return p;
     }
 };
@@ -591,6 +639,8 @@ static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, h
     P->vrec = P->pool.upload(P->hp.vrec, s);
     P->frec_off = P->pool.upload(P->hp.frec_off, s);
     P->vrec_off = P->pool.upload(P->hp.vrec_off, s);
+    P->prec = P->pool.upload(P->hp.prec, s);
+    P->level_lds = P->pool.upload(P->hp.level_lds, s);
     return P;
 }
 
@@ -800,13 +850,21 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
     int nt = persistent_threads(gs[0]->precision(), teams, n);
     hipStream_t s = lc.stream;
-    // LDS for the record offsets of the deepest schedule in the launch, up to 8192 levels (64 KiB)
-    int32_t max_levels = 0;
-    for (int i = 0; i < n; ++i) max_levels = std::max(max_levels, gs[i]->P->hp.exec_levels);
-    const int32_t lds_levels = std::min<int32_t>(max_levels, 8191);
-    const size_t lds_bytes = sizeof(int32_t) * 2 * size_t(lds_levels + 1);
+    // dynamic LDS: staging slots for the largest staged level in the launch, then per-level
+    // offsets and flags of the deepest schedule (up to 4096 levels; deeper schedules read them
+    // from memory). Kept within 64 KiB so two 512-thread workgroups fit a compute unit.
+    int32_t max_levels = 0, stage_cap = 0;
+    for (int i = 0; i < n; ++i) {
+        max_levels = std::max(max_levels, gs[i]->P->hp.exec_levels);
+        stage_cap = std::max(stage_cap, gs[i]->P->hp.stage_slots);
+    }
+    const size_t slot_bytes = sizeof(typename PP::S) * 2 * size_t(stage_cap);
+    int32_t lds_levels = std::min<int32_t>(max_levels, 4095);
+    if (slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1) > (size_t(64) << 10)) lds_levels = 0;
+    const size_t lds_bytes = slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1);
     HIPCHK(hipEventRecord(lc.k0, s));
-#define FASTLBP_LAUNCH(DA, TE, NT_) k_persistent<PP, DA, TE, NT_><<<n, NT_, lds_bytes, s>>>(dd, lds_levels)
+#define FASTLBP_LAUNCH(DA, TE, NT_) \
+    k_persistent<PP, DA, TE, NT_><<<n, NT_, lds_bytes, s>>>(dd, lds_levels, stage_cap)
     bool launched = false;
     if constexpr (std::is_same<PP, PolLog32>::value) {
         if (nt == 1024) {
