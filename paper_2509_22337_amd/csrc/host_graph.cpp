@@ -393,10 +393,16 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     // factors, its variables have at most kStagedEdges written edges each and none takes the
     // wavefront path, and its written edges fit kMaxStageSlots
     level_lds.assign(exec_levels, 0);
-    prec.assign(vrec.size(), 0);
+    prec.clear();
     stage_slots = 0;
-    std::vector<int32_t> edge_slot(g.E, -1);
-    for (int32_t L = 0; L < exec_levels; ++L) {
+    // a level may be staged only if it is narrow: no level of a wide plan is (and its variable
+    // records are not built)
+    bool any_narrow = false;
+    for (int32_t L = 0; L < exec_levels && !any_narrow; ++L)
+        any_narrow = frec_off[L + 1] - frec_off[L] <= kMaxStageSlots;
+    if (any_narrow) prec.assign(vrec.size(), 0);
+    std::vector<int32_t> edge_slot(any_narrow ? g.E : 0, -1);
+    for (int32_t L = 0; any_narrow && L < exec_levels; ++L) {
         bool ok = fac_lvl_off[FB_WAVE][L + 1] == fac_lvl_off[FB_WAVE][L] &&
                   fac_lvl_off[FB_BLOCK][L + 1] == fac_lvl_off[FB_BLOCK][L] &&
                   var_lvl_off[VB_WAVE][L + 1] == var_lvl_off[VB_WAVE][L];
