@@ -39,13 +39,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# Measured HBM traffic of one k_persistent launch in the default configuration (256 queries, 8
+# Measured HBM traffic of one k_persistent launch in the default configuration (512 queries, 8
 # iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
-# (profiles/k_persistent_smartfl_200k_batch256.md). Valid only for the kernel sources it was taken
+# (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "3f90e89278e46dec968b9e0b8fe1a7e50bee3ca22336475f47c81e38eb1f9873",
-                   "bytes_per_launch": 80803996138.6, "raw_bytes_per_launch": 51457663445.0,
-                   "queries": 256, "step_iters": 8}
+TRAFFIC_DEFAULT = {"sources_sha256": "3a450a13a0bc7d3f2ec9532cd8651438966219c5d3da420e726d8bdc2d9a0015",
+                   "bytes_per_launch": 187441500441.7, "raw_bytes_per_launch": 115642240298.0,
+                   "queries": 512, "step_iters": 8}
 
 
 def kernel_sources_sha256() -> str:
@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256, help="queries per batched step")
+    ap.add_argument("--batch", type=int, default=512, help="queries per batched step (512: two per compute unit)")
     ap.add_argument("--step-iters", type=int, default=8, help="iterations per server launch")
     ap.add_argument("--fp64-queries", type=int, default=3)
     ap.add_argument("--max-iters", type=int, default=None, help="override the workload's 500")
