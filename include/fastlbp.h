@@ -163,6 +163,29 @@ int fastlbp_graph_clone(fastlbp_graph_t src, fastlbp_graph_t *out);
  * E_BAD_SCHEDULE, E_OOM, E_DEVICE. */
 int fastlbp_schedule_set(fastlbp_graph_t g, int32_t kind, const int32_t *edge_rank, int32_t *num_levels_out);
 
+/* Sets a general update strategy: a preorder on the edges given as equivalence classes and strict
+ * precedences between classes (the Hasse diagram of Section 4.2, Algorithm 2's input, or any
+ * relation whose transitive closure is the intended order).
+ *   num_classes            1 .. 16384
+ *   edge_class [E]         class of each edge, in [0, num_classes)
+ *   arcs [2*num_arcs]      pairs (x, y): every edge of class x is updated strictly before every edge
+ *                          of class y; may be NULL when num_arcs = 0
+ * The preorder must satisfy Definition 2: an edge and every edge of its N_E (Definition 1) lie in
+ * comparable classes (pairs involving a PRIOR edge are exempt, their messages being constant).
+ * The classes are then ordered by a deterministic topological sort (smallest class first among
+ * those ready) and the result equals fastlbp_schedule_set(RANKED) with those ranks; by Theorem 2
+ * the messages do not depend on which topological order is taken. Errors: E_INVALID_ARG (ids out
+ * of range), E_TOO_LARGE (too many classes), E_BAD_SCHEDULE (a cycle, a class before itself, or
+ * incomparable dependent edges), E_OOM, E_DEVICE. */
+int fastlbp_schedule_set_classes(fastlbp_graph_t g, int32_t num_classes, const int32_t *edge_class, int32_t num_arcs,
+                                 const int32_t *arcs, int32_t *num_levels_out);
+
+/* Host-only form of the above: writes the ranks [E] the preorder induces (its topological order),
+ * or fails as above. factor_types may be NULL (then no edge is treated as PRIOR). */
+int fastlbp_classes_to_ranks(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                             const int32_t *edge_vars, const uint8_t *factor_types, int32_t num_classes,
+                             const int32_t *edge_class, int32_t num_arcs, const int32_t *arcs, int32_t *edge_rank);
+
 /* Copies the level of every edge [E] (0-based) of the current schedule. */
 int fastlbp_schedule_levels(fastlbp_graph_t g, int32_t *level_of_edge);
 

@@ -274,3 +274,74 @@ def check_theorem2(w, ranks, level, NE=None):
             if ranks[e] <= ranks[e2] and not level[e2] >= level[e]:
                 bad.append((e, e2))
     return bad
+
+
+# ----------------------------------------------------------------------------------------------
+# General preorders (Definition 2): classes of edges and strict arcs between classes
+# ----------------------------------------------------------------------------------------------
+
+def class_reach(num_classes, arcs):
+    """reach[x] = set of classes strictly after x (transitive closure of the arcs, by search)."""
+    succ = [[] for _ in range(num_classes)]
+    for x, y in arcs:
+        succ[int(x)].append(int(y))
+    reach = []
+    for x in range(num_classes):
+        seen, stack = set(), list(succ[x])
+        while stack:
+            y = stack.pop()
+            if y not in seen:
+                seen.add(y)
+                stack.extend(succ[y])
+        reach.append(seen)
+    return reach
+
+
+def preorder_is_acyclic(num_classes, arcs):
+    reach = class_reach(num_classes, arcs)
+    return all(x not in reach[x] for x in range(num_classes))
+
+
+def preorder_legal(w, edge_class, num_classes, arcs, NE=None):
+    """Definition 2: every edge e1 and every e2 in N_E(e1) lie in comparable classes. Pairs with a
+    PRIOR edge are skipped (a PRIOR message is constant, so its position cannot matter)."""
+    NE = edge_neighbourhood(w) if NE is None else NE
+    reach = class_reach(num_classes, arcs)
+    edge_fac = np.repeat(np.arange(len(w.fac_type)), np.diff(w.fac_off))
+    prior = w.fac_type[edge_fac] == 0
+    for e1 in range(len(edge_class)):
+        if prior[e1]:
+            continue
+        for e2 in NE[e1]:
+            if prior[e2]:
+                continue
+            x, y = int(edge_class[e1]), int(edge_class[e2])
+            if not (x == y or y in reach[x] or x in reach[y]):
+                return False
+    return True
+
+
+def linear_extension(num_classes, arcs, rng=None):
+    """Position of each class in a topological order of the arcs: smallest ready class first, or a
+    random ready class when rng is given."""
+    succ = [[] for _ in range(num_classes)]
+    indeg = [0] * num_classes
+    for x, y in arcs:
+        succ[int(x)].append(int(y))
+        indeg[int(y)] += 1
+    ready = [c for c in range(num_classes) if indeg[c] == 0]
+    pos = [-1] * num_classes
+    k = 0
+    while ready:
+        if rng is None:
+            c = min(ready)
+        else:
+            c = ready[int(rng.integers(0, len(ready)))]
+        ready.remove(c)
+        pos[c] = k
+        k += 1
+        for y in succ[c]:
+            indeg[y] -= 1
+            if indeg[y] == 0:
+                ready.append(y)
+    return np.array(pos, dtype=np.int64)

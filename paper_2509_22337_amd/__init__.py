@@ -73,7 +73,7 @@ class RunStats(ctypes.Structure):
 
 EXPORTS = [
     "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_clone", "fastlbp_graph_destroy",
-    "fastlbp_run_batch", "fastlbp_schedule_set",
+    "fastlbp_run_batch", "fastlbp_schedule_set", "fastlbp_schedule_set_classes", "fastlbp_classes_to_ranks",
     "fastlbp_schedule_levels", "fastlbp_analyze_levels", "fastlbp_graph_validate", "fastlbp_evidence_set",
     "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
     "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version", "fastlbp_server_options_default",
@@ -175,6 +175,22 @@ def analyze_levels(num_vars, fac_off, edge_var, edge_rank) -> tuple[np.ndarray, 
     n = ctypes.c_int32(0)
     _check(load().fastlbp_analyze_levels(int(num_vars), len(fo) - 1, _p(fo), _p(ev), _p(rk), _p(out), ctypes.byref(n)))
     return out, int(n.value)
+
+
+def classes_to_ranks(num_vars, fac_off, edge_var, fac_type, edge_class, num_classes: int, arcs=()) -> np.ndarray:
+    """Ranks [E] induced by a class preorder (see fastlbp_classes_to_ranks); raises FastLBPError with
+    code E_BAD_SCHEDULE for an illegal or cyclic preorder."""
+    fo = np.ascontiguousarray(fac_off, dtype=np.int64)
+    ev = np.ascontiguousarray(edge_var, dtype=np.int32)
+    ft = None if fac_type is None else np.ascontiguousarray(fac_type, dtype=np.uint8)
+    ec = np.ascontiguousarray(edge_class, dtype=np.int32)
+    if len(ec) != len(ev):
+        raise FastLBPError(E_INVALID_ARG, "edge_class must have one entry per edge")
+    ar = np.ascontiguousarray(np.asarray(arcs, dtype=np.int32).reshape(-1, 2))
+    out = np.zeros(len(ev), dtype=np.int32)
+    _check(load().fastlbp_classes_to_ranks(int(num_vars), len(fo) - 1, _p(fo), _p(ev), _p(ft), int(num_classes),
+                                           _p(ec), len(ar), _p(ar) if len(ar) else None, _p(out)))
+    return out
 
 
 def run_batch(graphs, max_iters: int, tol: float = 0.0, damping: float = 0.0) -> list:
@@ -307,6 +323,17 @@ class Graph:
         n = ctypes.c_int32(0)
         _check(load().fastlbp_schedule_set(self._h, int(kind), _p(rk), ctypes.byref(n)))
         return int(n.value)
+
+    def schedule_set_classes(self, edge_class, num_classes: int, arcs=()) -> int:
+        """General preorder: class per edge and strict precedences (x, y) between classes."""
+        ec = np.ascontiguousarray(edge_class, dtype=np.int32)
+        if len(ec) != self.num_edges:
+            raise FastLBPError(E_INVALID_ARG, "edge_class must have one entry per edge")
+        ar = np.ascontiguousarray(np.asarray(arcs, dtype=np.int32).reshape(-1, 2))
+        n = ctypes.c_int32(0)
+        _check(load().fastlbp_schedule_set_classes(self._h, int(num_classes), _p(ec), len(ar),
+                                                   _p(ar) if len(ar) else None, ctypes.byref(n)))
+        return n.value
 
     def schedule_levels(self) -> np.ndarray:
         out = np.zeros(self.num_edges, dtype=np.int32)

@@ -20,6 +20,11 @@ int validate_graph(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *
 int32_t analyze_levels(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const int32_t *rank,
                        std::vector<int32_t> &level);
 
+// Largest number of classes of a general preorder (the comparability check keeps a C x C bit matrix).
+constexpr int32_t kMaxClasses = 16384;
+int classes_to_ranks(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, int32_t C,
+                     const int32_t *edge_class, int32_t A, const int32_t *arcs, std::vector<int32_t> &rank);
+
 struct HostGraph {
     int32_t V = 0, F = 0;
     int64_t E = 0;

@@ -1,5 +1,7 @@
 // Host-side graph preparation (the Initialization and Dependency Analysis stages of Section 4.1).
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -223,6 +225,143 @@ void HostGraph::build(int32_t V_, int32_t F_, const int64_t *off, const int32_t 
             else
                 prior_fin[v] += std::log2(p) - std::log2(1.0 - p);
         }
+}
+
+// A general preorder as classes and strict arcs between them (Definition 2): checks that the arcs
+// form a DAG and that every edge is comparable with every edge of its N_E (Definition 1) that is
+// not a PRIOR edge, then ranks the classes by a deterministic topological order (Kahn's algorithm,
+// smallest class first). Returns 0 or an error code (message set).
+int classes_to_ranks(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, int32_t C,
+                     const int32_t *edge_class, int32_t A, const int32_t *arcs, std::vector<int32_t> &rank) {
+    const int64_t E = off[F];
+    if (C < 1 || C > kMaxClasses || A < 0 || (E > 0 && !edge_class) || (A > 0 && !arcs)) {
+        set_error("need 1 <= num_classes <= " + std::to_string(kMaxClasses) + " and the class and arc arrays");
+        return C > kMaxClasses ? FASTLBP_E_TOO_LARGE : FASTLBP_E_INVALID_ARG;
+    }
+    for (int64_t e = 0; e < E; ++e)
+        if (edge_class[e] < 0 || edge_class[e] >= C) {
+            set_error("edge " + std::to_string(e) + " has a class out of range");
+            return FASTLBP_E_INVALID_ARG;
+        }
+    std::vector<std::vector<int32_t>> succ(C);
+    std::vector<int32_t> indeg(C, 0);
+    for (int32_t i = 0; i < A; ++i) {
+        const int32_t x = arcs[2 * i], y = arcs[2 * i + 1];
+        if (x < 0 || x >= C || y < 0 || y >= C) {
+            set_error("arc " + std::to_string(i) + " names a class out of range");
+            return FASTLBP_E_INVALID_ARG;
+        }
+        if (x == y) {
+            set_error("arc " + std::to_string(i) + " puts a class strictly before itself");
+            return FASTLBP_E_BAD_SCHEDULE;
+        }
+        succ[x].push_back(y);
+        indeg[y]++;
+    }
+    // topological order, smallest available class first
+    std::vector<int32_t> order, pos(C, -1);
+    order.reserve(C);
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> ready;
+    for (int32_t c = 0; c < C; ++c)
+        if (indeg[c] == 0) ready.push(c);
+    while (!ready.empty()) {
+        const int32_t c = ready.top();
+        ready.pop();
+        pos[c] = int32_t(order.size());
+        order.push_back(c);
+        for (int32_t y : succ[c])
+            if (--indeg[y] == 0) ready.push(y);
+    }
+    if (int32_t(order.size()) != C) {
+        set_error("the class arcs contain a cycle");
+        return FASTLBP_E_BAD_SCHEDULE;
+    }
+    // reachability (class x strictly before class y), in reverse topological order
+    const size_t W = (size_t(C) + 63) / 64;
+    std::vector<uint64_t> reach(size_t(C) * W, 0);
+    for (int32_t i = C - 1; i >= 0; --i) {
+        const int32_t c = order[i];
+        uint64_t *rc = &reach[size_t(c) * W];
+        for (int32_t y : succ[c]) {
+            rc[y >> 6] |= uint64_t(1) << (y & 63);
+            const uint64_t *ry = &reach[size_t(y) * W];
+            for (size_t k = 0; k < W; ++k) rc[k] |= ry[k];
+        }
+    }
+    auto before = [&](int32_t x, int32_t y) { return (reach[size_t(x) * W + (y >> 6)] >> (y & 63)) & 1; };
+    auto comparable = [&](int32_t x, int32_t y) { return x == y || before(x, y) || before(y, x); };
+    // Definition 2: e1 = (a, v), e2 = (a2, u) with u in N(a) \ v and a2 in N(u) \ a. Per variable u,
+    // the distinct classes of its non-PRIOR edges; per factor, those of its other edges.
+    std::vector<int32_t> edge_fac(E);
+    for (int32_t a = 0; a < F; ++a)
+        for (int64_t e = off[a]; e < off[a + 1]; ++e) edge_fac[e] = a;
+    auto is_prior = [&](int64_t e) { return ft && ft[edge_fac[e]] == FASTLBP_PRIOR; };
+    std::vector<int32_t> voff(size_t(V) + 1, 0), vedge(E);
+    for (int64_t e = 0; e < E; ++e) voff[ev[e] + 1]++;
+    for (int32_t v = 0; v < V; ++v) voff[v + 1] += voff[v];
+    {
+        std::vector<int32_t> fill(voff.begin(), voff.end() - 1);
+        for (int64_t e = 0; e < E; ++e) vedge[fill[ev[e]]++] = int32_t(e);
+    }
+    // distinct classes (with counts) of each variable's non-PRIOR edges
+    std::vector<int32_t> vcls_off(size_t(V) + 1, 0), vcls, vcnt;
+    {
+        std::vector<int32_t> tmp;
+        for (int32_t v = 0; v < V; ++v) {
+            tmp.clear();
+            for (int32_t q = voff[v]; q < voff[v + 1]; ++q)
+                if (!is_prior(vedge[q])) tmp.push_back(edge_class[vedge[q]]);
+            std::sort(tmp.begin(), tmp.end());
+            for (size_t i = 0; i < tmp.size();) {
+                size_t j = i;
+                while (j < tmp.size() && tmp[j] == tmp[i]) ++j;
+                vcls.push_back(tmp[i]);
+                vcnt.push_back(int32_t(j - i));
+                i = j;
+            }
+            vcls_off[v + 1] = int32_t(vcls.size());
+        }
+    }
+    std::vector<int32_t> fcls, fcnt;
+    std::vector<uint8_t> checked;
+    for (int32_t a = 0; a < F; ++a) {
+        if (ft && ft[a] == FASTLBP_PRIOR) continue;
+        // distinct classes of a's edges, with counts
+        fcls.clear();
+        fcnt.clear();
+        {
+            std::vector<int32_t> tmp(edge_class + off[a], edge_class + off[a + 1]);
+            std::sort(tmp.begin(), tmp.end());
+            for (size_t i = 0; i < tmp.size();) {
+                size_t j = i;
+                while (j < tmp.size() && tmp[j] == tmp[i]) ++j;
+                fcls.push_back(tmp[i]);
+                fcnt.push_back(int32_t(j - i));
+                i = j;
+            }
+        }
+        for (int64_t eu = off[a]; eu < off[a + 1]; ++eu) {
+            const int32_t u = ev[eu], cu = edge_class[eu];
+            // e1 ranges over a's edges other than (a, u): a's classes, less cu if only (a, u) has it;
+            // e2 over u's non-PRIOR edges outside a: u's classes, less cu if only (a, u) has it
+            for (size_t i = 0; i < fcls.size(); ++i) {
+                const int32_t x = fcls[i];
+                if (x == cu && fcnt[i] == 1) continue;
+                for (int32_t q = vcls_off[u]; q < vcls_off[u + 1]; ++q) {
+                    const int32_t y = vcls[q];
+                    if (y == cu && vcnt[q] == 1) continue;
+                    if (!comparable(x, y)) {
+                        set_error("classes " + std::to_string(x) + " and " + std::to_string(y) +
+                                  " are incomparable but hold dependent edges (Definition 2)");
+                        return FASTLBP_E_BAD_SCHEDULE;
+                    }
+                }
+            }
+        }
+    }
+    rank.resize(E);
+    for (int64_t e = 0; e < E; ++e) rank[e] = pos[edge_class[e]];
+    return FASTLBP_OK;
 }
 
 int factor_bucket(int deg) {
@@ -475,5 +614,36 @@ extern "C" int fastlbp_analyze_levels(int32_t num_vars, int32_t num_factors, con
     int32_t n = fastlbp::analyze_levels(num_vars, num_factors, factor_offsets, edge_vars, edge_rank, level);
     if (E) std::memcpy(level_of_edge, level.data(), sizeof(int32_t) * E);
     if (num_levels_out) *num_levels_out = n;
+    return FASTLBP_OK;
+}
+
+extern "C" int fastlbp_classes_to_ranks(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                                        const int32_t *edge_vars, const uint8_t *factor_types, int32_t num_classes,
+                                        const int32_t *edge_class, int32_t num_arcs, const int32_t *arcs,
+                                        int32_t *edge_rank) {
+    fastlbp::clear_error();
+    if (num_vars < 0 || num_factors < 0 || !factor_offsets || (factor_offsets[num_factors] > 0 && !edge_rank)) {
+        fastlbp::set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    if (factor_offsets[0] != 0) {
+        fastlbp::set_error("factor_offsets[0] must be 0");
+        return FASTLBP_E_BAD_GRAPH;
+    }
+    for (int32_t a = 0; a < num_factors; ++a)
+        if (factor_offsets[a + 1] < factor_offsets[a]) {
+            fastlbp::set_error("factor_offsets must be non-decreasing");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    for (int64_t e = 0; e < factor_offsets[num_factors]; ++e)
+        if (edge_vars[e] < 0 || edge_vars[e] >= num_vars) {
+            fastlbp::set_error("variable id out of range");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    std::vector<int32_t> rank;
+    int rc = fastlbp::classes_to_ranks(num_vars, num_factors, factor_offsets, edge_vars, factor_types, num_classes,
+                                   edge_class, num_arcs, arcs, rank);
+    if (rc) return rc;
+    if (!rank.empty()) std::memcpy(edge_rank, rank.data(), sizeof(int32_t) * rank.size());
     return FASTLBP_OK;
 }

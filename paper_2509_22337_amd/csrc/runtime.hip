@@ -1242,6 +1242,21 @@ int fastlbp_schedule_set(fastlbp_graph_t g, int32_t kind, const int32_t *edge_ra
     return FASTLBP_OK;
 }
 
+int fastlbp_schedule_set_classes(fastlbp_graph_t g, int32_t num_classes, const int32_t *edge_class, int32_t num_arcs,
+                                 const int32_t *arcs, int32_t *num_levels_out) {
+    clear_error();
+    if (!g) {
+        set_error("graph is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    std::vector<int32_t> rank;
+    const HostGraph &hg = g->hg();
+    int rc = classes_to_ranks(hg.V, hg.F, hg.fac_off.data(), hg.edge_var.data(), hg.fac_type.data(), num_classes,
+                              edge_class, num_arcs, arcs, rank);
+    if (rc) return rc;
+    return fastlbp_schedule_set(g, FASTLBP_SCHED_RANKED, rank.data(), num_levels_out);
+}
+
 int fastlbp_schedule_levels(fastlbp_graph_t g, int32_t *level_of_edge) {
     clear_error();
     if (!g || (!level_of_edge && g->hg().E > 0)) {

@@ -254,6 +254,38 @@ def test_evidence_update_paths(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_class_preorder_schedule(precision):
+    # a general preorder (classes + arcs, Definition 2) set through the C ABI: levels equal the
+    # class-atomic analysis of its topological ranks, results equal the oracle under those ranks
+    from oracle import reference as R
+    rng = np.random.default_rng(17)
+    w = W.random_loopy(31, num_vars=80, num_factors=60, max_arity=4)
+    NE = R.edge_neighbourhood(w)
+    C = 12
+    cls = np.repeat(rng.integers(0, C, len(w.fac_type)), np.diff(w.fac_off)).astype(np.int32)
+    posc = np.argsort(rng.permutation(C))
+    prior = np.repeat(w.fac_type == W.PRIOR, np.diff(w.fac_off))
+    arcs = sorted({(int(cls[a]), int(cls[b])) if posc[cls[a]] < posc[cls[b]] else (int(cls[b]), int(cls[a]))
+                   for a in range(w.num_edges) for b in NE[a]
+                   if not prior[a] and not prior[b] and cls[a] != cls[b]})
+    ranks = F.classes_to_ranks(w.num_vars, w.fac_off, w.edge_var, w.fac_type, cls, C, arcs)
+    for executor in ("levels", "persistent"):
+        g = F.Graph.from_workload(w, precision=precision, executor=executor)
+        n = g.schedule_set_classes(cls, C, arcs)
+        lv = g.schedule_levels()
+        assert n == int(lv.max()) + 1
+        assert np.array_equal(lv, R.alg2_class_atomic(w, ranks, NE).astype(np.int32))
+        if w.evidence is not None:
+            g.evidence_array(w.evidence)
+        st = g.run(8, 0.0, 0.0)
+        m = g.marginals()
+        g.close()
+        om, _, ost = oracle.bp(w, 8, 0.0, 0.0, ranks=ranks)
+        _say("preorder", precision, executor, n, np.abs(m - om).max())
+        assert np.abs(m - om).max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_one_step_parity(precision):
     # same start state (including exact 0/1 messages), one iteration of a ranked schedule
     w = W.random_loopy(7, num_vars=60, num_factors=90, max_arity=9)
