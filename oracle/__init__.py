@@ -8,6 +8,7 @@ Contents
   * ``bp``                  plain FP64 loopy BP (C, single thread) - Eq.(1)-(3), schedule by Eq.(5)
                             and Definition 2, executed class by class without dependency analysis.
   * ``factor_messages``     Eq.(2) per factor type by disjoint-cube sums (C).
+  * ``terms_messages``      Eq.(4) for a factor given as weighted terms (C, plain sums).
   * ``reference``           pure-Python definitions used to pin the above: factor tables, Eq.(2) by
                             truth-table enumeration, Algorithm 1 on each type's term list, exact
                             marginals by enumeration, the edge dependency neighbourhood
@@ -53,8 +54,10 @@ def _load():
         lib.oracle_factor_messages.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P, P, P, P]
         lib.oracle_factor_messages.restype = None
         lib.oracle_bp.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32,
-                                  ctypes.c_double, ctypes.c_double, P, P, P, ctypes.POINTER(_Stats)]
+                                  ctypes.c_double, ctypes.c_double, P, P, P, ctypes.POINTER(_Stats), P, P, P]
         lib.oracle_bp.restype = ctypes.c_int
+        lib.oracle_terms_messages.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        lib.oracle_terms_messages.restype = None
         _lib = lib
     return _lib
 
@@ -74,6 +77,28 @@ def factor_messages(ftype: int, m0, m1, fparam: float = 0.0, eparam=None):
     o1 = np.zeros(d)
     lib.oracle_factor_messages(int(ftype), d, float(fparam), _ptr(ep), _ptr(m0), _ptr(m1), _ptr(o0), _ptr(o1))
     return o0, o1
+
+
+def terms_messages(weights, ind, m0, m1):
+    """Unnormalised Eq.(4) messages of a weighted-term factor (ind [l][d], -1 = wildcard)."""
+    lib = _load()
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    ti = np.ascontiguousarray(ind, dtype=np.int8)
+    m0 = np.ascontiguousarray(m0, dtype=np.float64)
+    m1 = np.ascontiguousarray(m1, dtype=np.float64)
+    d = len(m0)
+    o0 = np.zeros(d)
+    o1 = np.zeros(d)
+    lib.oracle_terms_messages(d, len(w), _ptr(w), _ptr(ti), _ptr(m0), _ptr(m1), _ptr(o0), _ptr(o1))
+    return o0, o1
+
+
+def _terms(w):
+    to = getattr(w, "term_off", None)
+    if to is None:
+        return None, None, None
+    return (np.ascontiguousarray(to, dtype=np.int64), np.ascontiguousarray(w.term_weight, dtype=np.float64),
+            np.ascontiguousarray(w.term_ind, dtype=np.int8))
 
 
 def bp(w, max_iters=None, tol=None, damping=None, ranks="auto", groups=None, evidence="auto", msg1=None):
@@ -108,9 +133,10 @@ def bp(w, max_iters=None, tol=None, damping=None, ranks="auto", groups=None, evi
     m0 = 1.0 - m1
     marg = np.zeros(w.num_vars)
     st = _Stats()
+    to, tw, ti = _terms(w)
     rc = lib.oracle_bp(int(w.num_vars), len(ft), _ptr(fac_off), _ptr(ev), _ptr(ft), _ptr(fp), _ptr(epar),
                        _ptr(rk), _ptr(gr), _ptr(evd), int(max_iters), float(tol), float(damping),
-                       _ptr(m0), _ptr(m1), _ptr(marg), ctypes.byref(st))
+                       _ptr(m0), _ptr(m1), _ptr(marg), ctypes.byref(st), _ptr(to), _ptr(tw), _ptr(ti))
     if rc != 0:
         raise RuntimeError(f"oracle_bp failed: {rc}")
     stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
@@ -135,7 +161,8 @@ def bp_pairs(w, msg0, msg1, max_iters, tol=0.0, damping=0.0, ranks=None, groups=
     m1 = np.array(msg1, dtype=np.float64, copy=True)
     marg = np.zeros(w.num_vars)
     st = _Stats()
+    to, tw, ti = _terms(w)
     lib.oracle_bp(int(w.num_vars), len(ft), _ptr(fac_off), _ptr(ev), _ptr(ft), _ptr(fp), _ptr(epar), _ptr(rk),
                   _ptr(gr), _ptr(evd), int(max_iters), float(tol), float(damping), _ptr(m0), _ptr(m1), _ptr(marg),
-                  ctypes.byref(st))
+                  ctypes.byref(st), _ptr(to), _ptr(tw), _ptr(ti))
     return marg, m0, m1, {f: getattr(st, f) for f, _ in _Stats._fields_}

@@ -42,7 +42,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { T_PRIOR = 0, T_AND = 1, T_OR = 2, T_NOT = 3, T_IMPLIES = 4, T_NOISY_OR = 5 };
+enum { T_PRIOR = 0, T_AND = 1, T_OR = 2, T_NOT = 3, T_IMPLIES = 4, T_NOISY_OR = 5, T_TERMS = 6 };
 
 /* ------------------------------------------------------------------------------------------ */
 /* Eq.(2) summed over the head for every head value, given the inputs' incoming messages.       */
@@ -158,6 +158,32 @@ void oracle_factor_messages(int type, int d, double fparam, const double *eparam
     free(buf);
 }
 
+/* Eq.(4) for a factor given as l weighted terms over its d edges: ind[t*d + k] is the value edge k
+ * is fixed to in term t, or -1 (any value). The message to edge v at value x sums, over the terms
+ * that allow x at v, the term's weight times the product over the other edges of the incoming
+ * message at the fixed value, or of the message's total for a wildcard. Written as the definition
+ * reads: O(l d^2). */
+void oracle_terms_messages(int d, int l, const double *weight, const int8_t *ind, const double *m0,
+                           const double *m1, double *out0, double *out1) {
+    for (int v = 0; v < d; ++v) {
+        double acc[2] = {0.0, 0.0};
+        for (int x = 0; x < 2; ++x)
+            for (int t = 0; t < l; ++t) {
+                int cv = ind[t * d + v];
+                if (cv != -1 && cv != x) continue;
+                double sm = weight[t];
+                for (int j = 0; j < d; ++j) {
+                    if (j == v) continue;
+                    int c = ind[t * d + j];
+                    sm *= (c == -1) ? (m0[j] + m1[j]) : (c == 1 ? m1[j] : m0[j]);
+                }
+                acc[x] += sm;
+            }
+        out0[v] = acc[0];
+        out1[v] = acc[1];
+    }
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Loopy BP driver                                                                            */
 /* ------------------------------------------------------------------------------------------ */
@@ -183,9 +209,16 @@ static void normalise(double *a0, double *a1) {
 int oracle_bp(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const uint8_t *fac_type,
               const double *fac_param, const double *edge_param, const int32_t *rank_of_edge,
               const int32_t *group_of_edge, const int8_t *evidence, int32_t max_iters, double tol, double damping,
-              double *msg0, double *msg1, double *marg1, oracle_stats *st) {
+              double *msg0, double *msg1, double *marg1, oracle_stats *st, const int64_t *term_off,
+              const double *term_weight, const int8_t *term_ind) {
     int64_t E = fac_off[F];
     memset(st, 0, sizeof(*st));
+    /* start of each factor's indicator rows (TERMS factors), term-major */
+    int64_t *ind_base = (int64_t *)calloc((size_t)F + 1, sizeof(int64_t));
+    for (int32_t a = 0; a < F; ++a) {
+        int64_t l = term_off ? term_off[a + 1] - term_off[a] : 0;
+        ind_base[a + 1] = ind_base[a] + l * (fac_off[a + 1] - fac_off[a]);
+    }
     /* edge -> factor */
     int32_t *edge_fac = (int32_t *)malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
     int dmax = 1;
@@ -283,7 +316,11 @@ int oracle_bp(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_
                     vf0[k] = p0; vf1[k] = p1;
                     ep[k] = edge_param ? edge_param[b + k] : 0.0;
                 }
-                oracle_factor_messages(fac_type[a], d, fac_param[a], ep, vf0, vf1, o0, o1);
+                if (fac_type[a] == T_TERMS)
+                    oracle_terms_messages(d, (int)(term_off[a + 1] - term_off[a]), term_weight + term_off[a],
+                                          term_ind + ind_base[a], vf0, vf1, o0, o1);
+                else
+                    oracle_factor_messages(fac_type[a], d, fac_param[a], ep, vf0, vf1, o0, o1);
                 /* keep the outputs of the class's edges of this factor */
                 while (i < ce && edge_fac[order[i]] == a) {
                     int64_t e = order[i];
@@ -336,6 +373,7 @@ int oracle_bp(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_
             st->marginal_contradictions++;
         }
     }
+    free(ind_base);
     free(edge_fac); free(var_off); free(var_edges); free(phi0); free(phi1); free(order);
     free(vf0); free(vf1); free(ep); free(o0); free(o1); free(new0); free(new1);
     return 0;

@@ -68,6 +68,34 @@ def eq2_messages(ftype: int, m0, m1, fparam: float = 0.0, eparam=None):
     return out[:, 0], out[:, 1]
 
 
+def terms_value(weights, ind, x) -> float:
+    """A weighted-term factor at assignment x: sum over terms of the weight times the indicator that
+    x agrees with every fixed value of the term (ind [l][d], -1 = wildcard)."""
+    tot = 0.0
+    for t in range(len(weights)):
+        if all(c == -1 or c == xi for c, xi in zip(ind[t], x)):
+            tot += float(weights[t])
+    return tot
+
+
+def eq2_messages_terms(weights, ind, m0, m1):
+    """Eq.(2) for a weighted-term factor by enumerating all 2^d assignments."""
+    d = len(m0)
+    m = np.stack([np.asarray(m0, float), np.asarray(m1, float)], axis=1)
+    out = np.zeros((d, 2))
+    for x in itertools.product((0, 1), repeat=d):
+        f = terms_value(weights, ind, x)
+        if f == 0.0:
+            continue
+        for v in range(d):
+            prod = f
+            for j in range(d):
+                if j != v:
+                    prod *= m[j, x[j]]
+            out[v, x[v]] += prod
+    return out[:, 0], out[:, 1]
+
+
 # ------------------------------------------------------------------------------------------------
 # Local-structure terms (Eq.(4)) and Algorithm 1
 # ------------------------------------------------------------------------------------------------

@@ -13,6 +13,11 @@ Graph format (all numpy arrays, factor-major CSR over edges, head = last edge of
     edge_param   float64[E]  NOISY_OR: per-parent activation probability; 0 elsewhere
     edge_rank    int32[E]    update-strategy rank per edge (None = flooding)
     evidence     int8[V]     -1 unobserved, 0 or 1 clamped
+  TERMS factors (a sum of weighted terms, Section 3.3) additionally use
+    term_off     int64[F+1]  term range of each factor (empty range for the other types)
+    term_weight  float64[T]  weight of each term (>= 0)
+    term_ind     int8[...]   per term, one indicator per edge of its factor (term-major): the value
+                             the edge's variable is fixed to in the term, or -1 for a wildcard
 
 The factor catalogue is the reading of the paper's probabilistic Horn constraints (Section 2.2,
 Section 3.3) used throughout this project; the workload shapes stand in for the SmartFL and BINGO
@@ -25,8 +30,9 @@ from typing import Optional
 
 import numpy as np
 
-PRIOR, AND, OR, NOT, IMPLIES, NOISY_OR = 0, 1, 2, 3, 4, 5
-TYPE_NAMES = {PRIOR: "PRIOR", AND: "AND", OR: "OR", NOT: "NOT", IMPLIES: "IMPLIES", NOISY_OR: "NOISY_OR"}
+PRIOR, AND, OR, NOT, IMPLIES, NOISY_OR, TERMS = 0, 1, 2, 3, 4, 5, 6
+TYPE_NAMES = {PRIOR: "PRIOR", AND: "AND", OR: "OR", NOT: "NOT", IMPLIES: "IMPLIES", NOISY_OR: "NOISY_OR",
+              TERMS: "TERMS"}
 
 
 @dataclass
@@ -44,6 +50,9 @@ class Workload:
     damping: float = 0.0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    term_off: Optional[np.ndarray] = None
+    term_weight: Optional[np.ndarray] = None
+    term_ind: Optional[np.ndarray] = None
 
     @property
     def num_factors(self) -> int:
@@ -532,6 +541,105 @@ def requery_clamps(w: Workload, marginals: np.ndarray, seed: int) -> tuple:
     else:
         x = (rng.random(len(v)) < marginals[v]).astype(np.int8)
     return v, x
+
+
+# ----------------------------------------------------------------------------------------------
+# Weighted-term factors
+# ----------------------------------------------------------------------------------------------
+
+def terms_of_type(ftype: int, d: int, fparam: float = 1.0):
+    """A deterministic or Horn factor of degree d (head last) written as disjoint weighted terms:
+    (weights [l], indicators [l][d], -1 = wildcard). NOISY_OR has no short disjoint form."""
+    n = d - 1
+    rows, wts = [], []
+    if ftype == NOT:
+        return np.array([1.0, 1.0]), np.array([[0, 1], [1, 0]], dtype=np.int8)
+    if ftype == PRIOR:
+        return np.array([1.0 - fparam, fparam]), np.array([[0], [1]], dtype=np.int8)
+    if ftype in (OR, AND):
+        idle, fire = (0, 1) if ftype == OR else (1, 0)
+        # no input fires: head = idle output; input k is the first to fire: head = fired output
+        rows.append([idle] * n + [idle if ftype == OR else 1])
+        wts.append(1.0)
+        for k in range(n):
+            rows.append([idle] * k + [fire] + [-1] * (n - k - 1) + [1 if ftype == OR else 0])
+            wts.append(1.0)
+        return np.array(wts), np.array(rows, dtype=np.int8)
+    if ftype == IMPLIES:
+        # body false (input k is the first 0): any head; body true: head 1 with p, head 0 with 1-p
+        for k in range(n):
+            rows.append([1] * k + [0] + [-1] * (n - k - 1) + [-1])
+            wts.append(1.0)
+        rows.append([1] * n + [1])
+        wts.append(fparam)
+        rows.append([1] * n + [0])
+        wts.append(1.0 - fparam)
+        return np.array(wts), np.array(rows, dtype=np.int8)
+    raise ValueError(f"no term form for type {ftype}")
+
+
+def as_terms(w: Workload) -> Workload:
+    """The same graph with every AND / OR / NOT / IMPLIES factor given as a TERMS factor (PRIOR and
+    NOISY_OR factors unchanged): both must produce the same messages."""
+    F = w.num_factors
+    deg = np.diff(w.fac_off)
+    ft = w.fac_type.copy()
+    toff = np.zeros(F + 1, dtype=np.int64)
+    wts, inds = [], []
+    for a in range(F):
+        t = int(w.fac_type[a])
+        if t in (AND, OR, NOT, IMPLIES):
+            p = float(w.fac_param[a]) if t == IMPLIES else 1.0
+            tw, ti = terms_of_type(t, int(deg[a]), p)
+            wts.append(tw)
+            inds.append(ti.reshape(-1))
+            ft[a] = TERMS
+            toff[a + 1] = toff[a] + len(tw)
+        else:
+            toff[a + 1] = toff[a]
+    out = Workload(num_vars=w.num_vars, fac_off=w.fac_off, edge_var=w.edge_var, fac_type=ft,
+                   fac_param=np.where(ft == TERMS, 0.0, w.fac_param), edge_param=w.edge_param,
+                   edge_rank=w.edge_rank, evidence=w.evidence, max_iters=w.max_iters, tol=w.tol, damping=w.damping,
+                   name=w.name + "_terms", meta=dict(w.meta))
+    out.term_off = toff
+    out.term_weight = np.concatenate(wts) if wts else np.zeros(0)
+    out.term_ind = np.concatenate(inds).astype(np.int8) if inds else np.zeros(0, np.int8)
+    return out
+
+
+def random_terms(seed: int, num_vars: int = 40, num_factors: int = 50, max_arity: int = 6, max_terms: int = 8,
+                 prior_frac: float = 0.5, evidence_frac: float = 0.1, zero_weight_frac: float = 0.1) -> Workload:
+    """Random loopy graph of TERMS factors: arity 1..max_arity, 1..max_terms terms with random
+    indicators in {-1, 0, 1} and weights U(0, 1) (some exactly 0), plus PRIORs and a few clamps."""
+    rng = np.random.default_rng(seed)
+    b = _Builder(num_vars)
+    wts, inds = [], []
+    for _ in range(num_factors):
+        d = int(rng.integers(1, max_arity + 1))
+        vs = rng.choice(num_vars, size=d, replace=False)
+        l = int(rng.integers(1, max_terms + 1))
+        ti = rng.integers(-1, 2, (l, d)).astype(np.int8)
+        tw = rng.uniform(0.0, 1.0, l)
+        tw[rng.random(l) < zero_weight_frac] = 0.0
+        tw[int(rng.integers(0, l))] = max(tw.max(), 0.1)  # not all zero
+        b.add(TERMS, vs, 0.0)
+        wts.append(tw)
+        inds.append(ti.reshape(-1))
+    nterm = [len(x) for x in wts]
+    for v in rng.choice(num_vars, size=int(prior_frac * num_vars), replace=False):
+        b.add(PRIOR, [int(v)], float(rng.uniform(0.1, 0.9)))
+        nterm.append(0)
+    w = b.build(name="random_terms", max_iters=20, tol=0.0, damping=0.0)
+    w.edge_rank = None
+    w.term_off = _csr(np.array(nterm, dtype=np.int64))
+    w.term_weight = np.concatenate(wts)
+    w.term_ind = np.concatenate(inds).astype(np.int8)
+    ev = np.full(num_vars, -1, np.int8)
+    pick = rng.choice(num_vars, size=int(evidence_frac * num_vars), replace=False)
+    ev[pick] = rng.integers(0, 2, len(pick))
+    w.evidence = ev
+    w.meta = dict(seed=seed)
+    return w
 
 
 def config(name: str, seed: int = 0, scale: float = 1.0) -> Workload:
