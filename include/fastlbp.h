@@ -29,6 +29,9 @@
  *                       factor_params == NULL means p = 1).
  *     FASTLBP_NOISY_OR  degree >= 2; P(y = 0 | x) = (1 - leak) * prod_{j: x_j = 1} (1 - p_j),
  *                       leak = factor_params[a] in [0,1), p_j = edge_params[e] of input edge e.
+ *     FASTLBP_TERMS     degree 1..64, no head: a sum of 1..64 weighted terms (Section 3.3, Eq.(4)),
+ *                       f(x) = sum_t w_t * prod_k [c_tk = -1 or x_k = c_tk], given to
+ *                       fastlbp_graph_create_terms; messages as Eq.(4) (Algorithm 1's result).
  *   Readings where the paper is silent: messages start uniform; every stored message is
  *   normalised; a computed message whose two entries are both 0 is replaced by the uniform message
  *   and counted in fastlbp_run_stats.contradictions; damping mixes normalised old and new
@@ -73,7 +76,7 @@ enum {
 };
 
 enum { FASTLBP_PRIOR = 0, FASTLBP_AND = 1, FASTLBP_OR = 2, FASTLBP_NOT = 3, FASTLBP_IMPLIES = 4,
-       FASTLBP_NOISY_OR = 5 };
+       FASTLBP_NOISY_OR = 5, FASTLBP_TERMS = 6 };
 
 /* Message precision. FP64: messages stored as float64 log-likelihood ratios, factor algebra in
  * linear float64. FP32: messages stored as float32 log-likelihood ratios and the factor algebra in
@@ -89,6 +92,8 @@ enum { FASTLBP_SCHED_FLOODING = 0, FASTLBP_SCHED_RANKED = 1 };
 enum { FASTLBP_EXEC_AUTO = 0, FASTLBP_EXEC_LEVELS = 1, FASTLBP_EXEC_PERSISTENT = 2 };
 
 #define FASTLBP_MAX_DEGREE 16385 /* largest factor degree (inputs + head) */
+#define FASTLBP_MAX_TERM_DEGREE 64 /* largest degree of a TERMS factor */
+#define FASTLBP_MAX_TERMS 64       /* most terms of one TERMS factor */
 
 typedef struct fastlbp_options {
     int32_t precision;  /* FASTLBP_FP64 or FASTLBP_FP32 */
@@ -131,7 +136,7 @@ typedef struct fastlbp_graph *fastlbp_graph_t;
  *   num_vars, num_factors  sizes (>= 0)
  *   factor_offsets [F+1]   non-decreasing, factor_offsets[0] = 0, E = factor_offsets[F] < 2^31
  *   edge_vars [E]          variable of each edge, in [0, num_vars), no variable twice per factor
- *   factor_types [F]       FASTLBP_PRIOR .. FASTLBP_NOISY_OR
+ *   factor_types [F]       FASTLBP_PRIOR .. FASTLBP_NOISY_OR (TERMS: fastlbp_graph_create_terms)
  *   factor_params [F]      per type as above; may be NULL (PRIOR then defaults to 0.5, IMPLIES to 1)
  *   edge_params [E]        NOISY_OR activation of each input edge; may be NULL (then 1)
  * The schedule starts as FLOODING with uniform messages and no evidence.
@@ -139,6 +144,23 @@ typedef struct fastlbp_graph *fastlbp_graph_t;
 int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
                          const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
                          const double *edge_params, const fastlbp_options *opts, fastlbp_graph_t *out);
+
+/* As fastlbp_graph_create, with factors of type FASTLBP_TERMS (Section 3.3): a factor given as a
+ * sum of weighted terms, each term fixing some of the factor's variables to a value and leaving
+ * the others free (the indicator representation of Algorithm 1).
+ *   term_offsets [F+1]     term range of each factor: non-decreasing, term_offsets[0] = 0; empty
+ *                          for every factor that is not TERMS, 1..FASTLBP_MAX_TERMS for TERMS
+ *   term_weights [T]       weight of each term, finite and >= 0 (T = term_offsets[F])
+ *   term_indicators        for the terms of each factor in order, one int8 per edge of that factor
+ *                          (term-major): 0 or 1 = the edge's variable is fixed to that value in the
+ *                          term, -1 = wildcard; sum over factors of (terms x degree) entries
+ * The three arrays may be NULL when no factor is TERMS. A TERMS factor has degree
+ * 1..FASTLBP_MAX_TERM_DEGREE and no head: each edge receives Eq.(4). Errors: as
+ * fastlbp_graph_create; E_TOO_LARGE for a TERMS factor beyond the limits. */
+int fastlbp_graph_create_terms(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                               const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
+                               const double *edge_params, const int64_t *term_offsets, const double *term_weights,
+                               const int8_t *term_indicators, const fastlbp_options *opts, fastlbp_graph_t *out);
 
 void fastlbp_graph_destroy(fastlbp_graph_t g);
 

@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-from .workloads import AND, IMPLIES, NOISY_OR, NOT, OR, PRIOR  # noqa: F401  (factor tags)
+from .workloads import AND, IMPLIES, NOISY_OR, NOT, OR, PRIOR, TERMS  # noqa: F401  (factor tags)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfastlbp.so")
@@ -72,7 +72,8 @@ class RunStats(ctypes.Structure):
 
 
 EXPORTS = [
-    "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_clone", "fastlbp_graph_destroy",
+    "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_create_terms", "fastlbp_graph_clone",
+    "fastlbp_graph_destroy",
     "fastlbp_run_batch", "fastlbp_schedule_set", "fastlbp_schedule_set_classes", "fastlbp_classes_to_ranks",
     "fastlbp_schedule_levels", "fastlbp_analyze_levels", "fastlbp_graph_validate", "fastlbp_evidence_set",
     "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
@@ -105,6 +106,8 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_options_default.argtypes = [ctypes.POINTER(Options)]
     lib.fastlbp_options_default.restype = None
     lib.fastlbp_graph_create.argtypes = [i32, i32, P, P, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.fastlbp_graph_create_terms.argtypes = [i32, i32, P, P, P, P, P, P, P, P, ctypes.POINTER(Options),
+                                               ctypes.POINTER(P)]
     lib.fastlbp_graph_clone.argtypes = [P, ctypes.POINTER(P)]
     lib.fastlbp_run_batch.argtypes = [i32, P, i32, f64, f64, P]
     lib.fastlbp_graph_destroy.argtypes = [P]
@@ -241,7 +244,11 @@ class Graph:
     """A factor graph resident on one GPU (see include/fastlbp.h for the semantics of every call)."""
 
     def __init__(self, num_vars, fac_off, edge_var, fac_type, fac_param=None, edge_param=None, precision="fp64",
-                 executor="auto", device: int = 0, use_graph: bool = True, allocator: str = "torch", stream=None):
+                 executor="auto", device: int = 0, use_graph: bool = True, allocator: str = "torch", stream=None,
+                 term_off=None, term_weight=None, term_ind=None):
+        """term_off / term_weight / term_ind describe the TERMS factors (Eq.(4)): factor a owns terms
+        term_off[a] .. term_off[a+1], and term t of it fixes its edges to the row of term_ind that
+        follows the previous terms' rows (one int8 per edge, -1 = any value)."""
         lib = load()
         self._h = None
         fo, ev, ft, fp, ep = _arrays(fac_off, edge_var, fac_type, fac_param, edge_param)
@@ -270,8 +277,17 @@ class Graph:
         except ImportError:
             pass
         h = ctypes.c_void_p()
-        _check(lib.fastlbp_graph_create(self.num_vars, len(ft), _p(fo), _p(ev), _p(ft), _p(fp), _p(ep),
-                                        ctypes.byref(o), ctypes.byref(h)))
+        if term_off is None:
+            _check(lib.fastlbp_graph_create(self.num_vars, len(ft), _p(fo), _p(ev), _p(ft), _p(fp), _p(ep),
+                                            ctypes.byref(o), ctypes.byref(h)))
+        else:
+            to = np.ascontiguousarray(term_off, dtype=np.int64)
+            tw = np.ascontiguousarray(term_weight, dtype=np.float64)
+            ti = np.ascontiguousarray(term_ind, dtype=np.int8)
+            if len(to) != len(ft) + 1:
+                raise FastLBPError(E_INVALID_ARG, "term_off needs num_factors + 1 entries")
+            _check(lib.fastlbp_graph_create_terms(self.num_vars, len(ft), _p(fo), _p(ev), _p(ft), _p(fp), _p(ep),
+                                                  _p(to), _p(tw), _p(ti), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.precision = precision
         _LIVE.add(self)
@@ -292,6 +308,8 @@ class Graph:
 
     @classmethod
     def from_workload(cls, w, **kw) -> "Graph":
+        if getattr(w, "term_off", None) is not None:
+            kw = dict(kw, term_off=w.term_off, term_weight=w.term_weight, term_ind=w.term_ind)
         g = cls(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, **kw)
         if w.edge_rank is not None:
             g.schedule_set(SCHED_RANKED, w.edge_rank)

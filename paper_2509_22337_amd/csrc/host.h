@@ -13,7 +13,8 @@ void set_error(const std::string &msg);
 void clear_error();
 
 int validate_graph(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const uint8_t *fac_type,
-                   const double *fac_param, const double *edge_param);
+                   const double *fac_param, const double *edge_param, const int64_t *term_off = nullptr,
+                   const double *term_weight = nullptr, const int8_t *term_ind = nullptr);
 
 // Class-atomic Algorithm 2 over the preorder given by `rank` (nullptr = one class).
 // level[e] receives the level of every edge; returns the number of levels.
@@ -42,9 +43,16 @@ struct HostGraph {
     std::vector<int32_t> prior_pos, prior_neg;
     int32_t max_deg = 0;
     int64_t nonprior_edges = 0;
+    // TERMS factors: term range per factor, weights, and indicator rows (term t of factor a fixes
+    // edge k to term_ind[term_base[a] + (t - term_off[a]) * d_a + k], -1 = any value)
+    std::vector<int32_t> term_off;   // [F+1] (empty when the graph has no TERMS factor)
+    std::vector<double> term_weight; // [T]
+    std::vector<int8_t> term_ind;
+    std::vector<int32_t> term_base;  // [F+1]
 
     void build(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
                const double *ep);
+    void set_terms(const int64_t *toff, const double *tw, const int8_t *tind);
 };
 
 // Work lists for one schedule. Levels without any non-PRIOR edge are not executed.

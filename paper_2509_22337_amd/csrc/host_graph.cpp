@@ -25,7 +25,7 @@ namespace fastlbp {
 static bool bad_prob(double p) { return !(p >= 0.0 && p <= 1.0); }
 
 int validate_graph(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
-                   const double *ep) {
+                   const double *ep, const int64_t *toff, const double *tw, const int8_t *tind) {
     if (V < 0 || F < 0) {
         set_error("negative size");
         return FASTLBP_E_INVALID_ARG;
@@ -62,8 +62,26 @@ int validate_graph(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, 
         int64_t d = off[a + 1] - off[a];
         int t = ft[a];
         std::string where = " (factor " + std::to_string(a) + ")";
-        if (t > FASTLBP_NOISY_OR) {
+        if (t > FASTLBP_TERMS) {
             set_error("unknown factor type" + where);
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        const int64_t nt = toff ? toff[a + 1] - toff[a] : 0;
+        if (t == FASTLBP_TERMS) {
+            if (!toff) {
+                set_error("TERMS factors need term data (fastlbp_graph_create_terms)" + where);
+                return FASTLBP_E_BAD_GRAPH;
+            }
+            if (d < 1 || nt < 1) {
+                set_error("TERMS needs degree >= 1 and at least one term" + where);
+                return FASTLBP_E_BAD_GRAPH;
+            }
+            if (d > FASTLBP_MAX_TERM_DEGREE || nt > FASTLBP_MAX_TERMS) {
+                set_error("TERMS factor above FASTLBP_MAX_TERM_DEGREE or FASTLBP_MAX_TERMS" + where);
+                return FASTLBP_E_TOO_LARGE;
+            }
+        } else if (nt != 0) {
+            set_error("only TERMS factors take terms" + where);
             return FASTLBP_E_BAD_GRAPH;
         }
         if (t == FASTLBP_PRIOR && d != 1) {
@@ -74,7 +92,7 @@ int validate_graph(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, 
             set_error("NOT needs degree 2" + where);
             return FASTLBP_E_BAD_GRAPH;
         }
-        if (t != FASTLBP_PRIOR && t != FASTLBP_NOT && d < 2) {
+        if (t != FASTLBP_PRIOR && t != FASTLBP_NOT && t != FASTLBP_TERMS && d < 2) {
             set_error("AND/OR/IMPLIES/NOISY_OR need degree >= 2" + where);
             return FASTLBP_E_BAD_GRAPH;
         }
@@ -104,6 +122,34 @@ int validate_graph(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, 
             for (int64_t e = off[a]; e + 1 < off[a + 1]; ++e)
                 if (bad_prob(ep[e])) {
                     set_error("noisy-or activation outside [0,1]" + where);
+                    return FASTLBP_E_BAD_GRAPH;
+                }
+    }
+    if (toff) {
+        if (toff[0] != 0) {
+            set_error("term_offsets[0] must be 0");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+        for (int32_t a = 0; a < F; ++a)
+            if (toff[a + 1] < toff[a]) {
+                set_error("term_offsets must be non-decreasing");
+                return FASTLBP_E_BAD_GRAPH;
+            }
+        const int64_t T = toff[F];
+        if (T > 0 && (!tw || !tind)) {
+            set_error("term_weights and term_indicators are required");
+            return FASTLBP_E_INVALID_ARG;
+        }
+        for (int64_t t = 0; t < T; ++t)
+            if (!(tw[t] >= 0.0 && tw[t] < __builtin_inf())) {
+                set_error("term weight " + std::to_string(t) + " not finite and >= 0");
+                return FASTLBP_E_BAD_GRAPH;
+            }
+        int64_t k = 0;
+        for (int32_t a = 0; a < F; ++a)
+            for (int64_t q = 0; q < (toff[a + 1] - toff[a]) * (off[a + 1] - off[a]); ++q, ++k)
+                if (tind[k] < -1 || tind[k] > 1) {
+                    set_error("term indicator outside {-1, 0, 1} (factor " + std::to_string(a) + ")");
                     return FASTLBP_E_BAD_GRAPH;
                 }
     }
@@ -364,6 +410,25 @@ int classes_to_ranks(int32_t V, int32_t F, const int64_t *off, const int32_t *ev
     return FASTLBP_OK;
 }
 
+void HostGraph::set_terms(const int64_t *toff, const double *tw, const int8_t *tind) {
+    term_off.clear();
+    term_weight.clear();
+    term_ind.clear();
+    term_base.clear();
+    if (!toff || toff[F] == 0) return;
+    term_off.resize(size_t(F) + 1);
+    for (int32_t a = 0; a <= F; ++a) term_off[a] = int32_t(toff[a]);
+    term_weight.assign(tw, tw + toff[F]);
+    term_base.resize(size_t(F) + 1);
+    int64_t n = 0;
+    for (int32_t a = 0; a < F; ++a) {
+        term_base[a] = int32_t(n);
+        n += (toff[a + 1] - toff[a]) * (fac_off[a + 1] - fac_off[a]);
+    }
+    term_base[F] = int32_t(n);
+    term_ind.assign(tind, tind + n);
+}
+
 int factor_bucket(int deg) {
     if (deg <= kThreadMaxDeg) return FB_THREAD;
     if (deg <= kWaveMaxDeg) return FB_WAVE;
@@ -398,7 +463,8 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     for (int32_t a = 0; a < g.F; ++a) {
         if (g.fac_type[a] == FASTLBP_PRIOR) continue;
         int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
-        int bucket = factor_bucket(int(d));
+        const bool terms = g.fac_type[a] == FASTLBP_TERMS;
+        int bucket = terms ? FB_TERMS : factor_bucket(int(d));
         int32_t prev = -1;
         // levels of a factor's edges in ascending order of level, each level once
         std::vector<int32_t> lv;
@@ -413,6 +479,10 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             double per_edge = 4.0 + sizeof(Belief) + msg_bytes + (flooding ? 0 : 4) +
                               (g.fac_type[a] == FASTLBP_NOISY_OR ? param_bytes : 0);
             bytes_per_iter += 4 + 8 + 1 + param_bytes + per_edge * double(d);
+            if (terms) {  // term range, indicator base, per term: weight and one indicator per edge
+                const double l = double(g.term_off[a + 1] - g.term_off[a]);
+                bytes_per_iter += 8 + 4 + l * (param_bytes / 2 + double(d));
+            }
         }
     }
     // variables whose incoming messages a level writes: their beliefs are refreshed after it
@@ -544,6 +614,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     for (int32_t L = 0; any_narrow && L < exec_levels; ++L) {
         bool ok = fac_lvl_off[FB_WAVE][L + 1] == fac_lvl_off[FB_WAVE][L] &&
                   fac_lvl_off[FB_BLOCK][L + 1] == fac_lvl_off[FB_BLOCK][L] &&
+                  fac_lvl_off[FB_TERMS][L + 1] == fac_lvl_off[FB_TERMS][L] &&
                   var_lvl_off[VB_WAVE][L + 1] == var_lvl_off[VB_WAVE][L];
         int32_t slots = 0;
         for (int32_t i = frec_off[L]; i < frec_off[L + 1]; ++i) {

@@ -517,6 +517,55 @@ __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typena
     }
 }
 
+// Factor given as weighted terms (Eq.(4)): one wavefront per factor, lane k owning edge k (degree
+// <= 64). The message to edge k at value x sums, over the terms that admit x at k, the term's
+// weight times the product over the other edges of their v->f message at the value the term fixes
+// (1 where the term leaves the edge free, the messages being normalised). For each term the product
+// over the other edges is the exclusive prefix times the exclusive suffix across the lanes, so it
+// costs O(log degree) steps and no division. A null v->f message (two exact zeros) makes every
+// other edge's message a contradiction, as in the typed factors.
+template <class P, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_terms(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int lane,
+                                             int level, Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    const int32_t b = g.fac_off[a];
+    const int32_t d = g.fac_off[a + 1] - b;
+    const int32_t t0 = g.term_off[a], t1 = g.term_off[a + 1];
+    const int32_t ib = g.term_base[a];
+    const bool mine = lane < d;
+    S old = (S)0;
+    bool nl = false;
+    V m0 = P::one(), m1 = P::one();
+    if (mine) {
+        old = g.msg[b + lane];
+        const S vf = v2f<P>(g.bel.ld(g.edge_var[b + lane]), old, nl);
+        if (!nl) P::leaf(vf, m0, m1);
+    }
+    const int nnull = wave_sum(nl ? 1 : 0);
+    V acc0 = P::zero(), acc1 = P::zero();
+    for (int32_t t = t0; t < t1; ++t) {
+        const int c = mine ? (int)g.term_ind[ib + int64_t(t - t0) * d + lane] : -1;
+        const V f = c < 0 ? P::one() : (c ? m1 : m0);
+        // inclusive prefix and suffix products over lanes 0..d-1 (lanes >= d hold the identity)
+        V p = f, q = f;
+        for (int k = 1; k < d; k <<= 1) {
+            const V pu = __shfl_up(p, k, 64);
+            const V qd = __shfl_down(q, k, 64);
+            if (lane >= k) p = P::mul(pu, p);
+            if (lane + k < 64) q = P::mul(q, qd);
+        }
+        V xp = __shfl_up(p, 1, 64), xq = __shfl_down(q, 1, 64);
+        if (lane == 0) xp = P::one();
+        if (lane == 63) xq = P::one();
+        const V x = P::mul(g.term_w[t], P::mul(xp, xq));
+        if (c != 1) acc0 = P::add(acc0, x);
+        if (c != 0) acc1 = P::add(acc1, x);
+    }
+    if (mine && is_active<ALL_ACTIVE>(g.edge_level, b + lane, level))
+        store_msg<P, DAMP>(g, b + lane, old, acc0, acc1, nnull - (nl ? 1 : 0) > 0, acc);
+}
+
 // Variable phase: B_v = phi_v + sum of the v's incoming non-PRIOR messages (float64, with counts).
 template <class P>
 __device__ __forceinline__ void belief_add(Belief &B, typename P::S l) {

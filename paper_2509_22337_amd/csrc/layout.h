@@ -108,7 +108,8 @@ constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 10
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
 constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record (VarRec::e)
 
-enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_COUNT = 3 };
+// FB_TERMS: factors given as weighted terms (one wavefront per factor, any degree up to 64)
+enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_TERMS = 3, FB_COUNT = 4 };
 enum { VB_THREAD = 0, VB_WAVE = 1, VB_COUNT = 2 };
 
 template <typename S, typename V>
@@ -126,6 +127,12 @@ struct DevGraph {
     GPtr<Belief> bel;               // [V]
     GPtr<S> msg;                    // [E]
     GPtr<const int32_t> edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
+    // weighted-term factors: term range per factor [F+1], weights in the value domain [T], start of
+    // each factor's indicator rows [F+1], indicators (row t of factor a: one entry per edge, -1 any)
+    GPtr<const int32_t> term_off;
+    GPtr<const V> term_w;
+    GPtr<const int32_t> term_base;
+    GPtr<const int8_t> term_ind;
     V damp_old;                // lambda in the value domain
     V damp_new;                // 1 - lambda in the value domain
     int32_t damped;            // lambda > 0 (a damped kernel leaves undamped runs' messages as computed)

@@ -77,6 +77,19 @@ __global__ __launch_bounds__(256) void k_fac_wave(DevGraph<typename P::S, typena
     flush_acc<256>(acc, st);
 }
 
+// Weighted-term factors, one wavefront each.
+template <class P, bool ALL, bool DAMP>
+__global__ __launch_bounds__(256) void k_fac_terms(DevGraph<typename P::S, typename P::V> g, const int32_t *list,
+                                                   int32_t count, int32_t level, RunState *st) {
+    if (st->done) return;
+    Acc acc = {0.0, 0u};
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < count; i += waves)
+        factor_terms<P, ALL, DAMP>(g, list[i], lane, level, acc);
+    flush_acc<256>(acc, st);
+}
+
 // One workgroup of NT threads per factor (1024 for float32; 512 for float64, whose factor code
 // needs more than the 128 registers a 1024-thread workgroup allows).
 template <class P, bool ALL, bool DAMP, int NT>
@@ -284,6 +297,11 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
                 for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
             }
             if (TEAMS) {
+                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS];
+                int32_t o0 = plan.fac_lvl_off[FB_TERMS][L], o1 = plan.fac_lvl_off[FB_TERMS][L + 1];
+                for (int32_t i = o0 + w; i < o1; i += NW) factor_terms<P, false, DAMP>(g, lst[i], lane, L, acc);
+            }
+            if (TEAMS) {
                 const GPtr<const int32_t> lst = plan.fac_list[FB_BLOCK];
                 int32_t o0 = plan.fac_lvl_off[FB_BLOCK][L], o1 = plan.fac_lvl_off[FB_BLOCK][L + 1];
                 for (int32_t i = o0; i < o1; ++i)
@@ -412,6 +430,9 @@ struct Structure {
     int32_t *fac_off = nullptr, *edge_var = nullptr, *var_off = nullptr, *var_edge = nullptr;
     uint8_t *fac_type = nullptr;
     void *fpar = nullptr, *epar = nullptr;
+    int32_t *term_off = nullptr, *term_base = nullptr;
+    void *term_w = nullptr;
+    int8_t *term_ind = nullptr;
     size_t msg_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
     size_t val_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
 };
@@ -426,7 +447,9 @@ struct Plan {
     int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
     int32_t *frec = nullptr, *vrec = nullptr, *frec_off = nullptr, *vrec_off = nullptr;
     int32_t *prec = nullptr, *level_lds = nullptr;
-    bool teams() const { return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty(); }
+    bool teams() const {
+        return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty() || !hp.fac_list[FB_TERMS].empty();
+    }
     DevPlan view() const {
         DevPlan p;
         p.num_levels = hp.exec_levels;
@@ -570,6 +593,10 @@ struct fastlbp_graph {
         g.bel = bel;
         g.msg = (typename PP::S *)msg;
         g.edge_level = P->edge_level;
+        g.term_off = S->term_off;
+        g.term_w = (const typename PP::V *)S->term_w;
+        g.term_base = S->term_base;
+        g.term_ind = S->term_ind;
         g.damped = damping > 0.0 ? 1 : 0;
         if (precision() == FASTLBP_FP32) {
             g.damp_old = (typename PP::V)(damping > 0 ? std::log2(damping) : -INFINITY);
@@ -614,6 +641,14 @@ static void upload_params(Structure &S, hipStream_t s, bool logd) {
     for (int64_t e = 0; e < S.hg.E; ++e) ep[e] = param_pair<V>(S.hg.edge_param[e], logd);
     S.fpar = S.pool.upload(fp, s);
     S.epar = S.pool.upload(ep, s);
+    if (!S.hg.term_off.empty()) {
+        std::vector<V> tw(S.hg.term_weight.size());
+        for (size_t t = 0; t < tw.size(); ++t) {
+            const double x = S.hg.term_weight[t];
+            tw[t] = logd ? (V)(x > 0 ? std::log2(x) : -INFINITY) : (V)x;
+        }
+        S.term_w = S.pool.upload(tw, s);
+    }
 }
 
 static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, hipStream_t s, int kind,
@@ -741,6 +776,9 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         o = pl.fac_lvl_off[FB_WAVE][L];
         n = pl.fac_lvl_off[FB_WAVE][L + 1] - o;
         if (n) k_fac_wave<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
+        o = pl.fac_lvl_off[FB_TERMS][L];
+        n = pl.fac_lvl_off[FB_TERMS][L + 1] - o;
+        if (n) k_fac_terms<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_TERMS] + o, n, L, g->st);
         o = pl.fac_lvl_off[FB_BLOCK][L];
         n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
         if (n)
@@ -1128,13 +1166,22 @@ static int finish_handle(fastlbp_graph *g) {
 int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
                          const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
                          const double *edge_params, const fastlbp_options *opts, fastlbp_graph_t *out) {
+    return fastlbp_graph_create_terms(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params,
+                                      edge_params, nullptr, nullptr, nullptr, opts, out);
+}
+
+int fastlbp_graph_create_terms(int32_t num_vars, int32_t num_factors, const int64_t *factor_offsets,
+                               const int32_t *edge_vars, const uint8_t *factor_types, const double *factor_params,
+                               const double *edge_params, const int64_t *term_offsets, const double *term_weights,
+                               const int8_t *term_indicators, const fastlbp_options *opts, fastlbp_graph_t *out) {
     clear_error();
     if (!out) {
         set_error("out is NULL");
         return FASTLBP_E_INVALID_ARG;
     }
     *out = nullptr;
-    int rc = validate_graph(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
+    int rc = validate_graph(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params,
+                            term_offsets, term_weights, term_indicators);
     if (rc) return rc;
     fastlbp_options o;
     fastlbp_options_default(&o);
@@ -1155,6 +1202,7 @@ int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *f
         S->precision = o.precision;
         S->pool.alloc = g->alloc;
         S->hg.build(num_vars, num_factors, factor_offsets, edge_vars, factor_types, factor_params, edge_params);
+        S->hg.set_terms(term_offsets, term_weights, term_indicators);
         const HostGraph &hg = S->hg;
         std::vector<int32_t> off32(hg.fac_off.begin(), hg.fac_off.end());
         S->fac_off = S->pool.upload(off32, s);
@@ -1162,6 +1210,11 @@ int fastlbp_graph_create(int32_t num_vars, int32_t num_factors, const int64_t *f
         S->fac_type = S->pool.upload(hg.fac_type, s);
         S->var_off = S->pool.upload(hg.var_off, s);
         S->var_edge = S->pool.upload(hg.var_edge, s);
+        if (!hg.term_off.empty()) {
+            S->term_off = S->pool.upload(hg.term_off, s);
+            S->term_base = S->pool.upload(hg.term_base, s);
+            S->term_ind = S->pool.upload(hg.term_ind, s);
+        }
         if (o.precision == FASTLBP_FP32)
             upload_params<float>(*S, s, true);
         else

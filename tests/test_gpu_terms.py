@@ -1,0 +1,185 @@
+"""GPU parity of weighted-term factors (Eq.(4)): the HIP path through fastlbp_graph_create_terms
+against the FP64 CPU oracle. Tolerances as for the typed factors: 1e-9 absolute in FP64, 1e-4 in
+FP32 (1e-12 / 1e-5 for a single iteration from a shared start state)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_22337_amd as F
+from oracle import reference as R
+from paper_2509_22337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-4}
+STEP_TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _run(w, precision, executor, ranks=None, max_iters=None, tol=None, damping=None, msg1=None):
+    g = F.Graph.from_workload(w, precision=precision, executor=executor)
+    if ranks is not None:
+        g.schedule_set(F.SCHED_RANKED, ranks)
+    if msg1 is not None:
+        g.messages_set(msg1)
+    st = g.run(w.max_iters if max_iters is None else max_iters, w.tol if tol is None else tol,
+               w.damping if damping is None else damping)
+    out = g.marginals(), g.messages_get(), st, g.schedule_levels()
+    g.close()
+    return out
+
+
+def _sensitive(w, ranks, max_iters, damping, eps, thr):
+    """Chaos guard: whether a perturbation eps of the start state moves the oracle's marginals by
+    more than thr (then end-to-end parity says nothing about the kernels)."""
+    a, _, _ = oracle.bp(w, max_iters, 0.0, damping, ranks=ranks)
+    m1 = 0.5 + eps * np.random.default_rng(0).standard_normal(w.num_edges)
+    b, _, _ = oracle.bp(w, max_iters, 0.0, damping, ranks=ranks, msg1=m1)
+    return np.abs(a - b).max() > thr
+
+
+def _start_state(w, seed):
+    rng = np.random.default_rng(seed)
+    p1 = rng.uniform(0, 1, w.num_edges)
+    p1[rng.random(w.num_edges) < 0.1] = 1.0
+    p1[rng.random(w.num_edges) < 0.1] = 0.0
+    pri = np.repeat(w.fac_type, np.diff(w.fac_off)) == W.PRIOR
+    p1[pri] = np.repeat(w.fac_param, np.diff(w.fac_off))[pri]
+    return p1
+
+
+def _wide_terms(seed, degrees, terms):
+    """TERMS factors of the given degrees and term counts over a pool of variables, plus PRIORs."""
+    rng = np.random.default_rng(seed)
+    nv = max(degrees) + 16
+    b = W._Builder(nv)
+    wts, inds, nterm = [], [], []
+    for d, l in zip(degrees, terms):
+        b.add(W.TERMS, rng.choice(nv, size=d, replace=False))
+        ti = rng.choice(np.array([-1, -1, 0, 1], np.int8), size=(l, d))
+        tw = rng.uniform(0.1, 1.0, l)
+        wts.append(tw)
+        inds.append(ti.reshape(-1))
+        nterm.append(l)
+    for v in range(0, nv, 3):
+        b.add(W.PRIOR, [v], float(rng.uniform(0.2, 0.8)))
+        nterm.append(0)
+    w = b.build(name="wide_terms", max_iters=10, tol=0.0, damping=0.0)
+    w.edge_rank = None
+    w.term_off = W._csr(np.array(nterm, dtype=np.int64))
+    w.term_weight = np.concatenate(wts)
+    w.term_ind = np.concatenate(inds).astype(np.int8)
+    w.evidence = None
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_terms_one_step(precision):
+    # one ranked iteration from the same start state (exact 0/1 messages included)
+    for seed in range(4):
+        w = W.random_terms(seed, num_vars=50, num_factors=70)
+        p1 = _start_state(w, seed + 100)
+        ranks = np.random.default_rng(seed).integers(0, 3, w.num_edges).astype(np.int32)
+        _, _, om1, ost = oracle.bp_pairs(w, 1 - p1, p1, 1, 0.0, 0.25, ranks=ranks)
+        for executor in ("levels", "persistent"):
+            _say("terms one-step", seed, precision, executor)
+            _, msgs, st, _ = _run(w, precision, executor, ranks=ranks, max_iters=1, tol=0.0, damping=0.25, msg1=p1)
+            assert np.abs(msgs - om1).max() <= STEP_TOL[precision], (seed, executor)
+            assert st["contradictions"] == ost["contradictions"], (seed, executor)
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_terms_loopy_flooding(executor, precision):
+    eps, thr = (1e-15, 1e-10) if precision == "fp64" else (1e-7, 1e-5)
+    checked = 0
+    for seed in range(8):
+        w = W.random_terms(seed)
+        if _sensitive(w, None, 30, 0.3, eps, thr):
+            continue
+        _say("terms flooding", seed, executor, precision)
+        m, msgs, st, _ = _run(w, precision, executor, max_iters=30, tol=0.0, damping=0.3)
+        om, omsg, ost = oracle.bp(w, 30, 0.0, 0.3, ranks=None)
+        assert np.abs(m - om).max() <= TOL[precision], seed
+        assert np.abs(msgs - omsg).max() <= TOL[precision], seed
+        assert st["iterations"] == ost["iterations"] == 30
+        checked += 1
+    assert checked >= 4
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+def test_terms_ranked_fp64(executor):
+    for seed in range(4):
+        w = W.random_terms(seed + 20)
+        ranks = np.random.default_rng(seed).permutation(w.num_edges).astype(np.int32)
+        if _sensitive(w, ranks, 20, 0.2, 1e-15, 1e-10):
+            continue
+        _say("terms ranked", seed, executor)
+        m, msgs, st, lv = _run(w, "fp64", executor, ranks=ranks, max_iters=20, tol=0.0, damping=0.2)
+        om, omsg, _ = oracle.bp(w, 20, 0.0, 0.2, ranks=ranks)
+        assert np.abs(m - om).max() <= 1e-9, seed
+        assert np.abs(msgs - omsg).max() <= 1e-9, seed
+        assert np.array_equal(lv, R.alg2_class_atomic(w, ranks).astype(np.int32))
+
+
+@pytest.mark.parametrize("executor", ["levels", "persistent"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_typed_graph_in_term_form(executor, precision):
+    # AND / OR / NOT / IMPLIES factors rewritten as TERMS factors: the GPU on the term form matches
+    # the oracle on the typed graph (NOISY_OR and PRIOR factors stay typed, so both paths mix)
+    for seed in range(3):
+        w = W.random_loopy(seed, num_vars=40, num_factors=50, max_arity=6)
+        wt = W.as_terms(w)
+        assert (wt.fac_type == W.TERMS).any()
+        _say("as_terms", seed, executor, precision)
+        m, msgs, _, _ = _run(wt, precision, executor, ranks=None, max_iters=1, tol=0.0, damping=0.0,
+                             msg1=_start_state(w, seed))
+        _, _, om1, _ = oracle.bp_pairs(w, 1 - _start_state(w, seed), _start_state(w, seed), 1, ranks=None)
+        assert np.abs(msgs - om1).max() <= STEP_TOL[precision], seed
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_terms_degree_and_term_limits(precision):
+    # degree 1 and 64 (every lane of the wavefront), 1 and 64 terms, and degrees around powers of two
+    degrees = [1, 64, 64, 2, 31, 32, 33, 63, 5]
+    terms = [3, 64, 1, 64, 7, 8, 9, 2, 64]
+    w = _wide_terms(3, degrees, terms)
+    p1 = _start_state(w, 9)
+    _, _, om1, ost = oracle.bp_pairs(w, 1 - p1, p1, 1, 0.0, 0.0, ranks=None)
+    for executor in ("levels", "persistent"):
+        _say("terms limits", precision, executor)
+        _, msgs, st, _ = _run(w, precision, executor, max_iters=1, tol=0.0, damping=0.0, msg1=p1)
+        assert np.abs(msgs - om1).max() <= STEP_TOL[precision], executor
+        assert st["contradictions"] == ost["contradictions"]
+
+
+def test_terms_rejects_bad_input():
+    w = W.random_terms(0)
+    with pytest.raises(F.FastLBPError):  # indicator outside {-1, 0, 1}
+        bad = w.term_ind.copy()
+        bad[0] = 2
+        F.Graph(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, term_off=w.term_off,
+                term_weight=w.term_weight, term_ind=bad)
+    with pytest.raises(F.FastLBPError):  # negative weight
+        bad = w.term_weight.copy()
+        bad[0] = -1.0
+        F.Graph(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, term_off=w.term_off,
+                term_weight=bad, term_ind=w.term_ind)
+    with pytest.raises(F.FastLBPError):  # TERMS factor without term data
+        F.Graph(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param)
+    big = _wide_terms(0, [65], [2])
+    with pytest.raises(F.FastLBPError):  # degree above the term-factor limit
+        F.Graph.from_workload(big)
