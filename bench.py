@@ -217,51 +217,67 @@ def serving_mix(F, W, args):
     return out
 
 
-def bingo_flooding(F, W, args):
+def flooding_runs(F, w, prec, steps, warmup, iters, label):
+    """`steps` timed cold runs of `iters` flooding iterations on the LEVELS executor."""
+    import torch
+    g = F.Graph.from_workload(w, precision=prec, executor="levels")
+    for s in range(warmup + steps):
+        if s == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dev_ms, upd, alg = 0.0, 0, 0.0
+        g.messages_reset()
+        st = g.run(iters, 0.0, 0.0)
+        if s >= warmup:
+            dev_ms += st["device_ms"]
+            upd += st["message_updates"]
+            alg += st["algorithmic_bytes_per_iter"] * st["iterations"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    r = dict(wall_s=wall, dev_ms=dev_ms, updates=upd, alg=alg, iters=st["iterations"], steps=steps,
+             mups=round(upd / wall, 1), us_per_iteration=round(dev_ms * 1e3 / (steps * st["iterations"]), 2))
+    log(f"{label} {prec}: {wall * 1e3 / steps:.1f} ms/run, {upd / wall / 1e9:.2f} G updates/s, "
+        f"{r['us_per_iteration']:.1f} us/iteration")
+    return r
+
+
+def bingo_flooding(F, W, args, terms=False):
     """One BINGO-shaped graph (2M tuples, 4M rules, 19M edges), flooding, FP32 messages, on the
     LEVELS executor: per iteration one launch per degree bucket and phase. A step is one run of
-    --max-iters (default 100) iterations; FP64 runs the same graph for the plain comparison."""
-    import torch
+    --max-iters (default 100) iterations; FP64 runs the same graph for the plain comparison.
+    terms: the 4M rule factors given as weighted terms (Eq.(4)) instead of AND factors; the typed
+    graph's FP32 time is reported beside it."""
     w = W.config("C3", seed=args.seed)
     iters = args.max_iters or 100
-    log(f"workload bingo: V={w.num_vars} F={w.num_factors} E={w.num_edges} (non-prior {w.nonprior_edges()})")
-    res = {}
-    for prec in ("fp32", "fp64"):
-        g = F.Graph.from_workload(w, precision=prec, executor="levels")
-        steps = args.steps if prec == "fp32" else 1
-        for s in range(args.warmup + steps):
-            if s == args.warmup:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                dev_ms, upd, alg = 0.0, 0, 0.0
-            g.messages_reset()
-            st = g.run(iters, 0.0, 0.0)
-            if s >= args.warmup:
-                dev_ms += st["device_ms"]
-                upd += st["message_updates"]
-                alg += st["algorithmic_bytes_per_iter"] * st["iterations"]
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        g.close()
-        res[prec] = dict(wall_s=wall, dev_ms=dev_ms, updates=upd, alg=alg, iters=st["iterations"], steps=steps)
-        log(f"bingo {prec}: {wall * 1e3 / steps:.1f} ms/run, {upd / wall / 1e9:.2f} G updates/s, "
-            f"{dev_ms * 1e3 / (steps * st['iterations']):.1f} us/iteration")
+    typed = None
+    if terms:
+        typed = flooding_runs(F, w, "fp32", args.steps, args.warmup, iters, "bingo typed")
+        w = W.as_terms(w)
+    log(f"workload bingo{'-terms' if terms else ''}: V={w.num_vars} F={w.num_factors} E={w.num_edges} "
+        f"(non-prior {w.nonprior_edges()})")
+    res = {prec: flooding_runs(F, w, prec, args.steps if prec == "fp32" else 1, args.warmup, iters, "bingo")
+           for prec in ("fp32", "fp64")}
     r = res["fp32"]
     achieved = r["alg"] / (r["dev_ms"] / 1e3) / 1e9
-    return {
+    name = "bingo_2M_tuples_4M_rules_19M_edges_flooding" + ("_rules_as_weighted_terms" if terms else "")
+    out = {
         "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
         "value": round(r["updates"] / r["wall_s"], 1), "unit": "message updates/s", "n_gpus": 1,
         "steps": r["steps"], "warmup": args.warmup, "ms_per_step": round(r["wall_s"] * 1e3 / r["steps"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "bingo_2M_tuples_4M_rules_19M_edges_flooding", "seed": args.seed,
-                   "num_vars": w.num_vars, "num_edges": w.num_edges, "iterations": iters, "executor": "levels"},
-        "us_per_iteration": round(r["dev_ms"] * 1e3 / (r["steps"] * r["iters"]), 2),
-        "plain_fp64": {"mups": round(res["fp64"]["updates"] / res["fp64"]["wall_s"], 1),
-                       "us_per_iteration": round(res["fp64"]["dev_ms"] * 1e3 / res["fp64"]["iters"], 2)},
+        "config": {"workload": name, "seed": args.seed, "num_vars": w.num_vars, "num_edges": w.num_edges,
+                   "iterations": iters, "executor": "levels"},
+        "us_per_iteration": r["us_per_iteration"],
+        "plain_fp64": {"mups": res["fp64"]["mups"], "us_per_iteration": res["fp64"]["us_per_iteration"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                      "kernel": "one iteration of the LEVELS executor (all kernels)"},
     }
+    if typed:
+        out["typed_fp32"] = {"mups": typed["mups"], "us_per_iteration": typed["us_per_iteration"]}
+        out["terms"] = int(len(w.term_weight))
+    return out
 
 
 def bingo_large(F, W, args):
@@ -344,10 +360,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
-    ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-large"], default="smartfl",
+    ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-terms", "bingo-large"],
+                    default="smartfl",
                     help="smartfl: batched queries of the 200k-variable SmartFL-shaped graph; serving: the "
                          "512-graph Poisson serving mix with warm re-queries; bingo: one 19M-edge "
-                         "BINGO-shaped graph, flooding, 100 iterations (wide-level kernels); bingo-large: "
+                         "BINGO-shaped graph, flooding, 100 iterations (wide-level kernels); bingo-terms: the "
+                         "same with its rule factors given as weighted terms; bingo-large: "
                          "one 190M-edge BINGO-shaped graph, 64 ordered groups, tol 1e-6, up to 200 iterations")
     ap.add_argument("--queries", type=int, default=512, help="graphs in the serving mix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -374,8 +392,8 @@ def main():
     from paper_2509_22337_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     F.load()
-    if args.workload == "bingo":
-        print(json.dumps(bingo_flooding(F, W, args)), flush=True)
+    if args.workload in ("bingo", "bingo-terms"):
+        print(json.dumps(bingo_flooding(F, W, args, terms=args.workload == "bingo-terms")), flush=True)
         return
     if args.workload == "bingo-large":
         print(json.dumps(bingo_large(F, W, args)), flush=True)

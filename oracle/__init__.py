@@ -9,6 +9,9 @@ Contents
                             and Definition 2, executed class by class without dependency analysis.
   * ``factor_messages``     Eq.(2) per factor type by disjoint-cube sums (C).
   * ``terms_messages``      Eq.(4) for a factor given as weighted terms (C, plain sums).
+  * ``factor_sample``       one flooding update of a sample of factors from a given state, factor by
+                            factor (C): the arithmetic of one ``bp`` iteration, for graphs too large
+                            for whole iterations.
   * ``reference``           pure-Python definitions used to pin the above: factor tables, Eq.(2) by
                             truth-table enumeration, Algorithm 1 on each type's term list, exact
                             marginals by enumeration, the edge dependency neighbourhood
@@ -58,6 +61,9 @@ def _load():
         lib.oracle_bp.restype = ctypes.c_int
         lib.oracle_terms_messages.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
         lib.oracle_terms_messages.restype = None
+        lib.oracle_factor_sample.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P,
+                                             ctypes.c_int32, P, P, P, P]
+        lib.oracle_factor_sample.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -166,3 +172,35 @@ def bp_pairs(w, msg0, msg1, max_iters, tol=0.0, damping=0.0, ranks=None, groups=
                   _ptr(gr), _ptr(evd), int(max_iters), float(tol), float(damping), _ptr(m0), _ptr(m1), _ptr(marg),
                   ctypes.byref(st), _ptr(to), _ptr(tw), _ptr(ti))
     return marg, m0, m1, {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+
+def factor_sample(w, msg1, factors, evidence="auto"):
+    """New messages P(x=1) of the edges of `factors` after one undamped flooding update from the
+    state msg1 (P(x=1) per edge; PRIOR edges hold their prior whatever msg1 says).
+    Returns (edges [n], P(x=1) [n], contradiction flags [n]) with the factors' edges in order."""
+    lib = _load()
+    if isinstance(evidence, str):
+        evidence = w.evidence
+    factors = np.ascontiguousarray(factors, dtype=np.int32)
+    fac_off = np.ascontiguousarray(w.fac_off, dtype=np.int64)
+    deg = fac_off[factors + 1] - fac_off[factors]
+    out_off = np.zeros(len(factors) + 1, dtype=np.int64)
+    np.cumsum(deg, out=out_off[1:])
+    edges = np.concatenate([np.arange(fac_off[a], fac_off[a + 1]) for a in factors]) if len(factors) else \
+        np.zeros(0, np.int64)
+    m1 = np.ascontiguousarray(msg1, dtype=np.float64)
+    m0 = 1.0 - m1
+    out1 = np.zeros(int(out_off[-1]))
+    contra = np.zeros(int(out_off[-1]), dtype=np.int8)
+    evd = None if evidence is None else np.ascontiguousarray(evidence, dtype=np.int8)
+    to, tw, ti = _terms(w)
+    rc = lib.oracle_factor_sample(int(w.num_vars), len(w.fac_type), _ptr(fac_off),
+                                  _ptr(np.ascontiguousarray(w.edge_var, dtype=np.int32)),
+                                  _ptr(np.ascontiguousarray(w.fac_type, dtype=np.uint8)),
+                                  _ptr(np.ascontiguousarray(w.fac_param, dtype=np.float64)),
+                                  _ptr(np.ascontiguousarray(w.edge_param, dtype=np.float64)), _ptr(evd), _ptr(m0),
+                                  _ptr(m1), _ptr(to), _ptr(tw), _ptr(ti), len(factors), _ptr(factors),
+                                  _ptr(out_off), _ptr(out1), _ptr(contra))
+    if rc != 0:
+        raise RuntimeError("oracle_factor_sample: a sampled factor is out of range or a PRIOR")
+    return edges, out1, contra.astype(bool)

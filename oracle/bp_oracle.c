@@ -202,6 +202,37 @@ static void normalise(double *a0, double *a1) {
     if (s > 0.0) { *a0 /= s; *a1 /= s; }
 }
 
+/* Unnormalised outputs (o0, o1) [d] of factor a in the state (msg0, msg1): the incoming
+ * variable-to-factor messages by Eq.(1), as a plain product over each variable's other edges
+ * (unary potential phi included), then Eq.(2) by factor type, or Eq.(4) for a TERMS factor. */
+static void factor_outputs(int32_t a, const int64_t *fac_off, const int32_t *edge_var, const uint8_t *fac_type,
+                           const double *fac_param, const double *edge_param, const int64_t *var_off,
+                           const int64_t *var_edges, const int32_t *edge_fac, const double *phi0, const double *phi1,
+                           const double *msg0, const double *msg1, const int64_t *term_off, const double *term_weight,
+                           const int8_t *term_ind, const int64_t *ind_base, double *vf0, double *vf1, double *ep,
+                           double *o0, double *o1) {
+    int64_t b = fac_off[a];
+    int d = (int)(fac_off[a + 1] - b);
+    for (int k = 0; k < d; ++k) {
+        int32_t u = edge_var[b + k];
+        double p0 = phi0[u], p1 = phi1[u];
+        for (int64_t q = var_off[u]; q < var_off[u + 1]; ++q) {
+            int64_t e2 = var_edges[q];
+            if (edge_fac[e2] == a) continue;
+            p0 *= msg0[e2];
+            p1 *= msg1[e2];
+            normalise(&p0, &p1); /* keeps the running product in range */
+        }
+        vf0[k] = p0; vf1[k] = p1;
+        ep[k] = edge_param ? edge_param[b + k] : 0.0;
+    }
+    if (fac_type[a] == T_TERMS)
+        oracle_terms_messages(d, (int)(term_off[a + 1] - term_off[a]), term_weight + term_off[a],
+                              term_ind + ind_base[a], vf0, vf1, o0, o1);
+    else
+        oracle_factor_messages(fac_type[a], d, fac_param[a], ep, vf0, vf1, o0, o1);
+}
+
 /* rank_of_edge: NULL = one class (flooding). group_of_edge: optional; when given, the groups it
  * defines replace the rank classes (used to check that executing the dependency-analysis levels
  * reproduces the class-by-class semantics). Messages msg0/msg1 [E] are read as the start state
@@ -301,26 +332,9 @@ int oracle_bp(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_
             while (i < ce) {
                 int32_t a = edge_fac[order[i]];
                 int64_t b = fac_off[a];
-                int d = (int)(fac_off[a + 1] - b);
-                /* Eq.(1): incoming variable-to-factor messages of factor a */
-                for (int k = 0; k < d; ++k) {
-                    int32_t u = edge_var[b + k];
-                    double p0 = phi0[u], p1 = phi1[u];
-                    for (int64_t q = var_off[u]; q < var_off[u + 1]; ++q) {
-                        int64_t e2 = var_edges[q];
-                        if (edge_fac[e2] == a) continue;
-                        p0 *= msg0[e2];
-                        p1 *= msg1[e2];
-                        normalise(&p0, &p1); /* keeps the running product in range */
-                    }
-                    vf0[k] = p0; vf1[k] = p1;
-                    ep[k] = edge_param ? edge_param[b + k] : 0.0;
-                }
-                if (fac_type[a] == T_TERMS)
-                    oracle_terms_messages(d, (int)(term_off[a + 1] - term_off[a]), term_weight + term_off[a],
-                                          term_ind + ind_base[a], vf0, vf1, o0, o1);
-                else
-                    oracle_factor_messages(fac_type[a], d, fac_param[a], ep, vf0, vf1, o0, o1);
+                factor_outputs(a, fac_off, edge_var, fac_type, fac_param, edge_param, var_off, var_edges, edge_fac,
+                               phi0, phi1, msg0, msg1, term_off, term_weight, term_ind, ind_base, vf0, vf1, ep, o0,
+                               o1);
                 /* keep the outputs of the class's edges of this factor */
                 while (i < ce && edge_fac[order[i]] == a) {
                     int64_t e = order[i];
@@ -377,4 +391,78 @@ int oracle_bp(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_
     free(edge_fac); free(var_off); free(var_edges); free(phi0); free(phi1); free(order);
     free(vf0); free(vf1); free(ep); free(o0); free(o1); free(new0); free(new1);
     return 0;
+}
+
+/* One flooding update of a sample of factors, computed one factor at a time from the state
+ * (msg0, msg1) [E] without running the whole iteration: for each factor in `sample` [n], the new
+ * normalised messages of its edges (a message whose two entries are both 0 becomes (1/2, 1/2) and
+ * sets its entry of `contra`), written to out1 (P(x=1)) from position out_off[i]. No damping. This
+ * is the same Eq.(1)-(2) / Eq.(4) arithmetic as an iteration of oracle_bp, restricted to the
+ * sampled factors, for graphs too large for the whole iteration. Returns 0 on success. */
+int oracle_factor_sample(int32_t V, int32_t F, const int64_t *fac_off, const int32_t *edge_var, const uint8_t *fac_type,
+                         const double *fac_param, const double *edge_param, const int8_t *evidence,
+                         const double *msg0_in, const double *msg1_in, const int64_t *term_off,
+                         const double *term_weight, const int8_t *term_ind, int32_t n, const int32_t *sample,
+                         const int64_t *out_off, double *out1, int8_t *contra) {
+    int64_t E = fac_off[F];
+    int64_t *ind_base = (int64_t *)calloc((size_t)F + 1, sizeof(int64_t));
+    for (int32_t a = 0; a < F; ++a) {
+        int64_t l = term_off ? term_off[a + 1] - term_off[a] : 0;
+        ind_base[a + 1] = ind_base[a] + l * (fac_off[a + 1] - fac_off[a]);
+    }
+    int32_t *edge_fac = (int32_t *)malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    int dmax = 1;
+    for (int32_t a = 0; a < F; ++a) {
+        for (int64_t e = fac_off[a]; e < fac_off[a + 1]; ++e) edge_fac[e] = a;
+        int d = (int)(fac_off[a + 1] - fac_off[a]);
+        if (d > dmax) dmax = d;
+    }
+    int64_t *var_off = (int64_t *)calloc((size_t)V + 1, sizeof(int64_t));
+    int64_t *var_edges = (int64_t *)malloc(sizeof(int64_t) * (size_t)(E > 0 ? E : 1));
+    for (int64_t e = 0; e < E; ++e) var_off[edge_var[e] + 1]++;
+    for (int32_t v = 0; v < V; ++v) var_off[v + 1] += var_off[v];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)V + 1));
+    memcpy(fill, var_off, sizeof(int64_t) * ((size_t)V + 1));
+    for (int64_t e = 0; e < E; ++e) var_edges[fill[edge_var[e]]++] = e;
+    free(fill);
+    double *phi0 = (double *)malloc(sizeof(double) * ((size_t)V + 1));
+    double *phi1 = (double *)malloc(sizeof(double) * ((size_t)V + 1));
+    for (int32_t v = 0; v < V; ++v) {
+        phi0[v] = 1.0; phi1[v] = 1.0;
+        if (evidence && evidence[v] == 0) phi1[v] = 0.0;
+        if (evidence && evidence[v] == 1) phi0[v] = 0.0;
+    }
+    /* PRIOR messages are the constant prior, whatever the state holds */
+    double *msg0 = (double *)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    double *msg1 = (double *)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    memcpy(msg0, msg0_in, sizeof(double) * (size_t)E);
+    memcpy(msg1, msg1_in, sizeof(double) * (size_t)E);
+    for (int32_t a = 0; a < F; ++a)
+        if (fac_type[a] == T_PRIOR) {
+            msg0[fac_off[a]] = 1.0 - fac_param[a];
+            msg1[fac_off[a]] = fac_param[a];
+        }
+    double *vf0 = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double *vf1 = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double *ep = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double *o0 = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double *o1 = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    int rc = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t a = sample[i];
+        if (a < 0 || a >= F || fac_type[a] == T_PRIOR) { rc = -1; break; }
+        factor_outputs(a, fac_off, edge_var, fac_type, fac_param, edge_param, var_off, var_edges, edge_fac, phi0,
+                       phi1, msg0, msg1, term_off, term_weight, term_ind, ind_base, vf0, vf1, ep, o0, o1);
+        int d = (int)(fac_off[a + 1] - fac_off[a]);
+        for (int k = 0; k < d; ++k) {
+            double n0 = o0[k], n1 = o1[k];
+            int c = !(n0 + n1 > 0.0);
+            if (c) { n0 = n1 = 0.5; } else normalise(&n0, &n1);
+            out1[out_off[i] + k] = n1;
+            contra[out_off[i] + k] = (int8_t)c;
+        }
+    }
+    free(ind_base); free(edge_fac); free(var_off); free(var_edges); free(phi0); free(phi1); free(msg0); free(msg1);
+    free(vf0); free(vf1); free(ep); free(o0); free(o1);
+    return rc;
 }

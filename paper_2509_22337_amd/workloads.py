@@ -580,30 +580,41 @@ def terms_of_type(ftype: int, d: int, fparam: float = 1.0):
 
 def as_terms(w: Workload) -> Workload:
     """The same graph with every AND / OR / NOT / IMPLIES factor given as a TERMS factor (PRIOR and
-    NOISY_OR factors unchanged): both must produce the same messages."""
+    NOISY_OR factors unchanged): both must produce the same messages. Factors of one type and
+    degree share one term pattern (IMPLIES differs only in its last two weights), so the rewrite is
+    done per (type, degree) group."""
     F = w.num_factors
-    deg = np.diff(w.fac_off)
-    ft = w.fac_type.copy()
-    toff = np.zeros(F + 1, dtype=np.int64)
-    wts, inds = [], []
-    for a in range(F):
-        t = int(w.fac_type[a])
-        if t in (AND, OR, NOT, IMPLIES):
-            p = float(w.fac_param[a]) if t == IMPLIES else 1.0
-            tw, ti = terms_of_type(t, int(deg[a]), p)
-            wts.append(tw)
-            inds.append(ti.reshape(-1))
-            ft[a] = TERMS
-            toff[a + 1] = toff[a] + len(tw)
-        else:
-            toff[a + 1] = toff[a]
+    deg = np.diff(w.fac_off).astype(np.int64)
+    ft0 = np.asarray(w.fac_type)
+    conv = np.isin(ft0, (AND, OR, NOT, IMPLIES))
+    nterm = np.zeros(F, dtype=np.int64)
+    nterm[conv & (ft0 == NOT)] = 2
+    nterm[conv & ((ft0 == OR) | (ft0 == AND))] = deg[conv & ((ft0 == OR) | (ft0 == AND))]
+    nterm[conv & (ft0 == IMPLIES)] = deg[conv & (ft0 == IMPLIES)] + 1
+    toff = _csr(nterm)
+    ioff = _csr(nterm * deg)
+    weights = np.zeros(int(toff[-1]))
+    inds = np.zeros(int(ioff[-1]), dtype=np.int8)
+    keys = np.unique(np.stack([ft0[conv].astype(np.int64), deg[conv]], axis=1), axis=0) if conv.any() else []
+    for t, d in keys:
+        sel = np.flatnonzero(conv & (ft0 == t) & (deg == d))
+        tw, ti = terms_of_type(int(t), int(d), 1.0)
+        l = len(tw)
+        assert l == nterm[sel[0]]
+        wmat = np.tile(tw, (len(sel), 1))
+        if t == IMPLIES:
+            wmat[:, -2] = w.fac_param[sel]
+            wmat[:, -1] = 1.0 - w.fac_param[sel]
+        weights[toff[sel][:, None] + np.arange(l)[None, :]] = wmat
+        inds[ioff[sel][:, None] + np.arange(l * int(d))[None, :]] = ti.reshape(-1)[None, :]
+    ft = np.where(conv, TERMS, ft0).astype(np.uint8)
     out = Workload(num_vars=w.num_vars, fac_off=w.fac_off, edge_var=w.edge_var, fac_type=ft,
-                   fac_param=np.where(ft == TERMS, 0.0, w.fac_param), edge_param=w.edge_param,
+                   fac_param=np.where(conv, 0.0, w.fac_param), edge_param=w.edge_param,
                    edge_rank=w.edge_rank, evidence=w.evidence, max_iters=w.max_iters, tol=w.tol, damping=w.damping,
                    name=w.name + "_terms", meta=dict(w.meta))
     out.term_off = toff
-    out.term_weight = np.concatenate(wts) if wts else np.zeros(0)
-    out.term_ind = np.concatenate(inds).astype(np.int8) if inds else np.zeros(0, np.int8)
+    out.term_weight = weights
+    out.term_ind = inds
     return out
 
 
