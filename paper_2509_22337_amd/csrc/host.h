@@ -49,6 +49,7 @@ struct HostGraph {
     std::vector<double> term_weight; // [T]
     std::vector<int8_t> term_ind;
     std::vector<int32_t> term_base;  // [F+1]
+    std::vector<uint16_t> term_mask; // [T] factors of degree <= 8: fixed-edge bits | value bits << 8
 
     void build(int32_t V, int32_t F, const int64_t *off, const int32_t *ev, const uint8_t *ft, const double *fp,
                const double *ep);

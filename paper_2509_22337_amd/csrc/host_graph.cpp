@@ -415,6 +415,7 @@ void HostGraph::set_terms(const int64_t *toff, const double *tw, const int8_t *t
     term_weight.clear();
     term_ind.clear();
     term_base.clear();
+    term_mask.clear();
     if (!toff || toff[F] == 0) return;
     term_off.resize(size_t(F) + 1);
     for (int32_t a = 0; a <= F; ++a) term_off[a] = int32_t(toff[a]);
@@ -427,6 +428,16 @@ void HostGraph::set_terms(const int64_t *toff, const double *tw, const int8_t *t
     }
     term_base[F] = int32_t(n);
     term_ind.assign(tind, tind + n);
+    term_mask.assign(term_weight.size(), 0);
+    for (int32_t a = 0; a < F; ++a) {
+        const int64_t d = fac_off[a + 1] - fac_off[a];
+        if (d > kThreadMaxDeg) continue;
+        for (int32_t t = term_off[a]; t < term_off[a + 1]; ++t)
+            for (int64_t k = 0; k < d; ++k) {
+                const int8_t c = term_ind[term_base[a] + (t - term_off[a]) * d + k];
+                if (c >= 0) term_mask[t] |= uint16_t((1u << k) | (unsigned(c) << (8 + k)));
+            }
+    }
 }
 
 int factor_bucket(int deg) {
@@ -464,7 +475,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         if (g.fac_type[a] == FASTLBP_PRIOR) continue;
         int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
         const bool terms = g.fac_type[a] == FASTLBP_TERMS;
-        int bucket = terms ? FB_TERMS : factor_bucket(int(d));
+        int bucket = terms ? (d <= kThreadMaxDeg ? FB_TERMS_THREAD : FB_TERMS_WAVE) : factor_bucket(int(d));
         int32_t prev = -1;
         // levels of a factor's edges in ascending order of level, each level once
         std::vector<int32_t> lv;
@@ -479,9 +490,11 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             double per_edge = 4.0 + sizeof(Belief) + msg_bytes + (flooding ? 0 : 4) +
                               (g.fac_type[a] == FASTLBP_NOISY_OR ? param_bytes : 0);
             bytes_per_iter += 4 + 8 + 1 + param_bytes + per_edge * double(d);
-            if (terms) {  // term range, indicator base, per term: weight and one indicator per edge
+            if (terms) {  // term range; per term its weight and indicators: a 16-bit mask pair
+                          // (thread path) or indicator base plus one byte per edge (wavefront path)
                 const double l = double(g.term_off[a + 1] - g.term_off[a]);
-                bytes_per_iter += 8 + 4 + l * (param_bytes / 2 + double(d));
+                bytes_per_iter += bucket == FB_TERMS_THREAD ? 8 + l * (param_bytes / 2 + 2)
+                                                             : 8 + 4 + l * (param_bytes / 2 + double(d));
             }
         }
     }
@@ -515,6 +528,13 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                     if (dx != dy) return dx < dy;
                     if (g.fac_type[x] != g.fac_type[y]) return g.fac_type[x] < g.fac_type[y];
                     return x < y;
+                });
+            else if (b == FB_TERMS_THREAD)  // by degree, then term count: a wavefront's loops agree
+                std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
+                    int dx = fdeg(x), dy = fdeg(y);
+                    if (dx != dy) return dx < dy;
+                    int lx = g.term_off[x + 1] - g.term_off[x], ly = g.term_off[y + 1] - g.term_off[y];
+                    return lx != ly ? lx < ly : x < y;
                 });
             else
                 std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
@@ -614,7 +634,8 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     for (int32_t L = 0; any_narrow && L < exec_levels; ++L) {
         bool ok = fac_lvl_off[FB_WAVE][L + 1] == fac_lvl_off[FB_WAVE][L] &&
                   fac_lvl_off[FB_BLOCK][L + 1] == fac_lvl_off[FB_BLOCK][L] &&
-                  fac_lvl_off[FB_TERMS][L + 1] == fac_lvl_off[FB_TERMS][L] &&
+                  fac_lvl_off[FB_TERMS_WAVE][L + 1] == fac_lvl_off[FB_TERMS_WAVE][L] &&
+                  fac_lvl_off[FB_TERMS_THREAD][L + 1] == fac_lvl_off[FB_TERMS_THREAD][L] &&
                   var_lvl_off[VB_WAVE][L + 1] == var_lvl_off[VB_WAVE][L];
         int32_t slots = 0;
         for (int32_t i = frec_off[L]; i < frec_off[L + 1]; ++i) {

@@ -566,6 +566,65 @@ __device__ __forceinline__ void factor_terms(const DevGraph<typename P::S, typen
         store_msg<P, DAMP>(g, b + lane, old, acc0, acc1, nnull - (nl ? 1 : 0) > 0, acc);
 }
 
+// Weighted-term factor of degree <= kThreadMaxDeg in one thread: for every term, a forward pass
+// gives the weight times the product over the edges before k and a backward pass the product over
+// the edges after k, so each term costs O(degree) and the factor O(terms x degree). Term t's
+// indicators come as the mask pair term_mask[t] (fixed edges, their values).
+template <class P, bool ALL_ACTIVE, bool DAMP>
+__device__ __forceinline__ void factor_terms_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t a,
+                                                    int level, Acc &acc) {
+    using S = typename P::S;
+    using V = typename P::V;
+    constexpr int K = kThreadMaxDeg;
+    const int32_t b = g.fac_off[a];
+    const int32_t d = g.fac_off[a + 1] - b;
+    const int32_t t0 = g.term_off[a], t1 = g.term_off[a + 1];
+    S old[K];
+    V m0[K], m1[K], a0[K], a1[K];
+    bool nl[K];
+    int nnull = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        m0[k] = P::one();
+        m1[k] = P::one();
+        a0[k] = P::zero();
+        a1[k] = P::zero();
+        old[k] = (S)0;
+        nl[k] = false;
+        if (k < d) {
+            old[k] = g.msg[b + k];
+            const S vf = v2f<P>(g.bel.ld(g.edge_var[b + k]), old[k], nl[k]);
+            if (!nl[k]) P::leaf(vf, m0[k], m1[k]);
+            nnull += nl[k] ? 1 : 0;
+        }
+    }
+    for (int32_t t = t0; t < t1; ++t) {
+        const unsigned mk = g.term_mask[t];
+        V pre[K];
+        V run = g.term_w[t];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            pre[k] = run;
+            if (k < d && ((mk >> k) & 1u)) run = P::mul(run, ((mk >> (8 + k)) & 1u) ? m1[k] : m0[k]);
+        }
+        V suf = P::one();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            if (k < d) {
+                const bool fix = (mk >> k) & 1u, val = (mk >> (8 + k)) & 1u;
+                const V x = P::mul(pre[k], suf);
+                if (!fix || !val) a0[k] = P::add(a0[k], x);
+                if (!fix || val) a1[k] = P::add(a1[k], x);
+                if (fix) suf = P::mul(suf, val ? m1[k] : m0[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < d && is_active<ALL_ACTIVE>(g.edge_level, b + k, level))
+            store_msg<P, DAMP>(g, b + k, old[k], a0[k], a1[k], nnull - (nl[k] ? 1 : 0) > 0, acc);
+}
+
 // Variable phase: B_v = phi_v + sum of the v's incoming non-PRIOR messages (float64, with counts).
 template <class P>
 __device__ __forceinline__ void belief_add(Belief &B, typename P::S l) {

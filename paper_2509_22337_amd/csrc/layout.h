@@ -108,8 +108,9 @@ constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 10
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
 constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record (VarRec::e)
 
-// FB_TERMS: factors given as weighted terms (one wavefront per factor, any degree up to 64)
-enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_TERMS = 3, FB_COUNT = 4 };
+// Factors given as weighted terms: FB_TERMS_THREAD one thread per factor (degree <= kThreadMaxDeg),
+// FB_TERMS_WAVE one wavefront per factor (degree up to 64)
+enum { FB_THREAD = 0, FB_WAVE = 1, FB_BLOCK = 2, FB_TERMS_WAVE = 3, FB_TERMS_THREAD = 4, FB_COUNT = 5 };
 enum { VB_THREAD = 0, VB_WAVE = 1, VB_COUNT = 2 };
 
 template <typename S, typename V>
@@ -133,6 +134,8 @@ struct DevGraph {
     GPtr<const V> term_w;
     GPtr<const int32_t> term_base;
     GPtr<const int8_t> term_ind;
+    // per term of a factor of degree <= 8: bit k = the term fixes edge k, bit 8 + k = to value 1
+    GPtr<const uint16_t> term_mask;
     V damp_old;                // lambda in the value domain
     V damp_new;                // 1 - lambda in the value domain
     int32_t damped;            // lambda > 0 (a damped kernel leaves undamped runs' messages as computed)

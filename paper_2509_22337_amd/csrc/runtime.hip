@@ -90,6 +90,18 @@ __global__ __launch_bounds__(256) void k_fac_terms(DevGraph<typename P::S, typen
     flush_acc<256>(acc, st);
 }
 
+// Weighted-term factors of degree <= 8, one thread each.
+template <class P, bool ALL, bool DAMP>
+__global__ __launch_bounds__(256) void k_fac_terms_thread(DevGraph<typename P::S, typename P::V> g,
+                                                          const int32_t *list, int32_t count, int32_t level,
+                                                          RunState *st) {
+    if (st->done) return;
+    Acc acc = {0.0, 0u};
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        factor_terms_thread<P, ALL, DAMP>(g, list[i], level, acc);
+    flush_acc<256>(acc, st);
+}
+
 // One workgroup of NT threads per factor (1024 for float32; 512 for float64, whose factor code
 // needs more than the 128 registers a 1024-thread workgroup allows).
 template <class P, bool ALL, bool DAMP, int NT>
@@ -297,8 +309,13 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
                 for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
             }
             if (TEAMS) {
-                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS];
-                int32_t o0 = plan.fac_lvl_off[FB_TERMS][L], o1 = plan.fac_lvl_off[FB_TERMS][L + 1];
+                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_THREAD];
+                int32_t o0 = plan.fac_lvl_off[FB_TERMS_THREAD][L], o1 = plan.fac_lvl_off[FB_TERMS_THREAD][L + 1];
+                for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_thread<P, false, DAMP>(g, lst[i], L, acc);
+            }
+            if (TEAMS) {
+                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_WAVE];
+                int32_t o0 = plan.fac_lvl_off[FB_TERMS_WAVE][L], o1 = plan.fac_lvl_off[FB_TERMS_WAVE][L + 1];
                 for (int32_t i = o0 + w; i < o1; i += NW) factor_terms<P, false, DAMP>(g, lst[i], lane, L, acc);
             }
             if (TEAMS) {
@@ -433,6 +450,7 @@ struct Structure {
     int32_t *term_off = nullptr, *term_base = nullptr;
     void *term_w = nullptr;
     int8_t *term_ind = nullptr;
+    uint16_t *term_mask = nullptr;
     size_t msg_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
     size_t val_bytes() const { return precision == FASTLBP_FP32 ? 4 : 8; }
 };
@@ -448,7 +466,8 @@ struct Plan {
     int32_t *frec = nullptr, *vrec = nullptr, *frec_off = nullptr, *vrec_off = nullptr;
     int32_t *prec = nullptr, *level_lds = nullptr;
     bool teams() const {
-        return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty() || !hp.fac_list[FB_TERMS].empty();
+        return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty() ||
+               !hp.fac_list[FB_TERMS_WAVE].empty() || !hp.fac_list[FB_TERMS_THREAD].empty();
     }
     DevPlan view() const {
         DevPlan p;
@@ -597,6 +616,7 @@ struct fastlbp_graph {
         g.term_w = (const typename PP::V *)S->term_w;
         g.term_base = S->term_base;
         g.term_ind = S->term_ind;
+        g.term_mask = S->term_mask;
         g.damped = damping > 0.0 ? 1 : 0;
         if (precision() == FASTLBP_FP32) {
             g.damp_old = (typename PP::V)(damping > 0 ? std::log2(damping) : -INFINITY);
@@ -776,9 +796,14 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         o = pl.fac_lvl_off[FB_WAVE][L];
         n = pl.fac_lvl_off[FB_WAVE][L + 1] - o;
         if (n) k_fac_wave<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_WAVE] + o, n, L, g->st);
-        o = pl.fac_lvl_off[FB_TERMS][L];
-        n = pl.fac_lvl_off[FB_TERMS][L + 1] - o;
-        if (n) k_fac_terms<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_TERMS] + o, n, L, g->st);
+        o = pl.fac_lvl_off[FB_TERMS_WAVE][L];
+        n = pl.fac_lvl_off[FB_TERMS_WAVE][L + 1] - o;
+        if (n) k_fac_terms<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_TERMS_WAVE] + o, n, L, g->st);
+        o = pl.fac_lvl_off[FB_TERMS_THREAD][L];
+        n = pl.fac_lvl_off[FB_TERMS_THREAD][L + 1] - o;
+        if (n)
+            k_fac_terms_thread<PP, ALL, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, P.fac_list[FB_TERMS_THREAD] + o, n,
+                                                                               L, g->st);
         o = pl.fac_lvl_off[FB_BLOCK][L];
         n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
         if (n)
@@ -1214,6 +1239,7 @@ int fastlbp_graph_create_terms(int32_t num_vars, int32_t num_factors, const int6
             S->term_off = S->pool.upload(hg.term_off, s);
             S->term_base = S->pool.upload(hg.term_base, s);
             S->term_ind = S->pool.upload(hg.term_ind, s);
+            S->term_mask = S->pool.upload(hg.term_mask, s);
         }
         if (o.precision == FASTLBP_FP32)
             upload_params<float>(*S, s, true);

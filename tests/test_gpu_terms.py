@@ -101,13 +101,14 @@ def test_terms_one_step(precision):
             assert st["contradictions"] == ost["contradictions"], (seed, executor)
 
 
+@pytest.mark.parametrize("arity", [6, 14])  # thread path only; thread and wavefront paths mixed
 @pytest.mark.parametrize("executor", ["levels", "persistent"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_terms_loopy_flooding(executor, precision):
+def test_terms_loopy_flooding(executor, precision, arity):
     eps, thr = (1e-15, 1e-10) if precision == "fp64" else (1e-7, 1e-5)
     checked = 0
     for seed in range(8):
-        w = W.random_terms(seed)
+        w = W.random_terms(seed, max_arity=arity)
         if _sensitive(w, None, 30, 0.3, eps, thr):
             continue
         _say("terms flooding", seed, executor, precision)
@@ -153,9 +154,10 @@ def test_typed_graph_in_term_form(executor, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_terms_degree_and_term_limits(precision):
-    # degree 1 and 64 (every lane of the wavefront), 1 and 64 terms, and degrees around powers of two
-    degrees = [1, 64, 64, 2, 31, 32, 33, 63, 5]
-    terms = [3, 64, 1, 64, 7, 8, 9, 2, 64]
+    # degree 1 and 64 (every lane of the wavefront), 1 and 64 terms, degrees around powers of two and
+    # both sides of the thread / wavefront boundary (8 / 9)
+    degrees = [1, 64, 64, 2, 31, 32, 33, 63, 5, 8, 8, 9, 9]
+    terms = [3, 64, 1, 64, 7, 8, 9, 2, 64, 64, 1, 64, 1]
     w = _wide_terms(3, degrees, terms)
     p1 = _start_state(w, 9)
     _, _, om1, ost = oracle.bp_pairs(w, 1 - p1, p1, 1, 0.0, 0.0, ranks=None)
