@@ -327,6 +327,89 @@ def bingo_large(F, W, args):
     }
 
 
+def alarm_ranking(F, W, args):
+    """BINGO's alarm-ranking loop (fastlbp_alarm_loop) on a BINGO-shaped derivation graph (68K
+    variables, 188K edges, args.alarms alarms) with a sampled ground truth. A step is one whole loop
+    (until every true alarm is inspected), cold, under BINGO's round-robin asynchronous order (SEQFIX,
+    FP32 messages); each round runs at most 500 iterations, tol 1e-6. The same loop also runs once
+    under flooding (synchronous) in FP32 and under SEQFIX in FP64, for the ranking metrics of
+    Section 5.3 (inversions, Rank-100%-T, Rank-90%-T)."""
+    import torch
+    w = W.alarm_graph(args.seed, num_alarms=args.alarms)
+    iters = args.max_iters or 500
+    total_true = int(w.labels.sum())
+    log(f"workload alarms: V={w.num_vars} F={w.num_factors} E={w.num_edges}, {len(w.alarms)} alarms, "
+        f"{total_true} true")
+    seq = W.seqfix_ranks(w)
+    res = {}
+    for name, prec, sched, steps in (("seqfix_fp32", "fp32", "seqfix", args.steps),
+                                      ("flooding_fp32", "fp32", "flooding", 1), ("seqfix_fp64", "fp64", "seqfix", 1)):
+        g = F.Graph.from_workload(w, precision=prec)
+        if sched == "seqfix":
+            g.schedule_set(F.SCHED_RANKED, seq)
+        for s in range(args.warmup + steps):
+            if s == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dev_ms, upd, rounds, alg = 0.0, 0, 0, 0.0
+            g.evidence_clear()
+            g.messages_reset()
+            order, _, st = g.alarm_loop(w.alarms, w.labels, max_rounds=None if s >= args.warmup else 2,
+                                        max_iters=iters, tol=1e-6, damping=0.0)
+            if s >= args.warmup:
+                dev_ms += st["device_ms"]
+                upd += st["message_updates"]
+                rounds += st["rounds"]
+                alg += st["algorithmic_bytes"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lv = g.schedule_levels().max() + 1 if sched == "seqfix" else 1
+        g.close()
+        lab = w.labels[order]
+        res[name] = dict(rounds=int(st["rounds"]), iterations=int(st["iterations"]),
+                         inversions=F.inversion_count(lab), rank_100=F.rank_of_fraction(lab, 1.0, total_true),
+                         rank_90=F.rank_of_fraction(lab, 0.9, total_true), mups=round(upd / wall, 1),
+                         ms_per_round=round(wall * 1e3 / max(1, rounds), 3), levels=int(lv),
+                         wall_s=wall, dev_ms=dev_ms, steps=steps, updates=upd, alg=alg)
+        log(f"{name}: {res[name]['rounds']} rounds, inversions {res[name]['inversions']}, Rank-100%-T "
+            f"{res[name]['rank_100']}, Rank-90%-T {res[name]['rank_90']}, {res[name]['ms_per_round']:.2f} ms/round, "
+            f"{upd / wall / 1e9:.3f} G updates/s")
+    r = res["seqfix_fp32"]
+    return w, {
+        "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
+        "value": r["mups"], "unit": "message updates/s", "n_gpus": 1, "steps": r["steps"], "warmup": args.warmup,
+        "ms_per_step": round(r["wall_s"] * 1e3 / r["steps"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"alarm_ranking_68k_vars_188k_edges_{len(w.alarms)}_alarms_seqfix", "seed": args.seed,
+                   "alarms": len(w.alarms), "true_alarms": total_true, "max_iters": iters, "tol": 1e-6,
+                   "levels": r["levels"]},
+        "ranking": {k: {f: v[f] for f in ("rounds", "iterations", "inversions", "rank_100", "rank_90", "mups",
+                                          "ms_per_round", "levels")} for k, v in res.items()},
+        "plain_fp64": {"mups": res["seqfix_fp64"]["mups"], "ms_per_round": res["seqfix_fp64"]["ms_per_round"]},
+        "roofline": {"bound": "hbm", "achieved": round(r["alg"] / (r["dev_ms"] / 1e3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r["alg"] / (r["dev_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 6),
+                     "traffic": None, "kernel": "k_persistent (one workgroup, SEQFIX levels) and the alarm picks"},
+    }
+
+
+def alarm_cpu_baseline(w, budget_s: float):
+    """The oracle's alarm loop under SEQFIX (single thread) for as many rounds as fit in about
+    `budget_s` seconds."""
+    import oracle
+    seq = np.arange(w.num_edges, dtype=np.int32)
+    t0 = time.perf_counter()
+    _, _, st = oracle.bp(w, max_iters=1, tol=0.0, ranks=seq)
+    one = time.perf_counter() - t0
+    it_budget = max(1, int(budget_s / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    marg, m0, m1, st = oracle.bp_pairs(w, np.full(w.num_edges, 0.5), np.full(w.num_edges, 0.5),
+                                       min(500, it_budget), 1e-6, 0.0, ranks=seq)
+    dt = time.perf_counter() - t0
+    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle",
+                sample=f"the first round of the loop (SEQFIX, tol 1e-6, at most {min(500, it_budget)} iterations): "
+                       f"{st['iterations']} iterations, {st['message_updates']} updates in {dt:.1f} s")
+
+
 def cpu_baseline(w, budget_s: float):
     """The oracle (single thread) on a bounded sample: as many full iterations of the same graph,
     schedule and evidence as fit in about `budget_s` seconds."""
@@ -360,12 +443,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
-    ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-terms", "bingo-large"],
+    ap.add_argument("--alarms", type=int, default=300, help="alarms of the alarm-ranking workload")
+    ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-terms", "bingo-large", "alarms"],
                     default="smartfl",
                     help="smartfl: batched queries of the 200k-variable SmartFL-shaped graph; serving: the "
                          "512-graph Poisson serving mix with warm re-queries; bingo: one 19M-edge "
                          "BINGO-shaped graph, flooding, 100 iterations (wide-level kernels); bingo-terms: the "
-                         "same with its rule factors given as weighted terms; bingo-large: "
+                         "same with its rule factors given as weighted terms; alarms: BINGO's alarm-ranking "
+                         "loop on a 68K-variable derivation graph (SEQFIX vs flooding); bingo-large: "
                          "one 190M-edge BINGO-shaped graph, 64 ordered groups, tol 1e-6, up to 200 iterations")
     ap.add_argument("--queries", type=int, default=512, help="graphs in the serving mix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -392,6 +477,12 @@ def main():
     from paper_2509_22337_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     F.load()
+    if args.workload == "alarms":
+        w, out = alarm_ranking(F, W, args)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = alarm_cpu_baseline(w, args.cpu_budget)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload in ("bingo", "bingo-terms"):
         print(json.dumps(bingo_flooding(F, W, args, terms=args.workload == "bingo-terms")), flush=True)
         return

@@ -87,9 +87,11 @@ enum { FASTLBP_SCHED_FLOODING = 0, FASTLBP_SCHED_RANKED = 1 };
 
 /* Executor. LEVELS: one kernel launch per level and phase over the whole GPU (wide levels,
  * flooding). PERSISTENT: one workgroup runs every level and iteration of the run in a single
- * launch with workgroup barriers between phases (narrow levels, small graphs). AUTO picks by the
- * width of the levels. Both give the same messages up to floating-point rounding order. */
-enum { FASTLBP_EXEC_AUTO = 0, FASTLBP_EXEC_LEVELS = 1, FASTLBP_EXEC_PERSISTENT = 2 };
+ * launch with workgroup barriers between phases (narrow levels, small graphs). HYBRID: LEVELS for
+ * the wide levels, and each run of consecutive narrow levels in one single-workgroup launch per
+ * iteration (schedules that mix a few wide levels with many narrow ones). AUTO picks by the width
+ * of the levels. All give the same messages up to floating-point rounding order. */
+enum { FASTLBP_EXEC_AUTO = 0, FASTLBP_EXEC_LEVELS = 1, FASTLBP_EXEC_PERSISTENT = 2, FASTLBP_EXEC_HYBRID = 3 };
 
 #define FASTLBP_MAX_DEGREE 16385 /* largest factor degree (inputs + head) */
 #define FASTLBP_MAX_TERM_DEGREE 64 /* largest degree of a TERMS factor */
@@ -117,7 +119,7 @@ typedef struct fastlbp_run_stats {
     double residual;             /* residual of the last iteration */
     int64_t contradictions;      /* messages replaced by uniform during the run */
     int32_t levels;              /* levels per iteration (dependency analysis) */
-    int32_t executor;            /* FASTLBP_EXEC_LEVELS or FASTLBP_EXEC_PERSISTENT */
+    int32_t executor;            /* FASTLBP_EXEC_LEVELS, _PERSISTENT or _HYBRID */
     double algorithmic_bytes_per_iter; /* bytes one iteration must move at minimum: for every executed
                                     * factor and variable task its structure, parameters, beliefs
                                     * and messages read once, and every written message stored once */
@@ -261,6 +263,39 @@ int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1);
 
 /* Resets every message to uniform (cold start). */
 int fastlbp_messages_reset(fastlbp_graph_t g);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Alarm ranking: BINGO's interactive loop (Section 5.2.2, Section 5.3)                         */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct fastlbp_alarm_stats {
+    int32_t rounds;           /* alarms inspected */
+    int32_t true_found;       /* true alarms among them */
+    int64_t iterations;       /* BP iterations over all rounds */
+    int64_t message_updates;  /* factor-to-variable updates over all rounds */
+    double device_ms;         /* device time of the BP runs and alarm picks (HIP events) */
+    double wall_ms;           /* host wall time of the whole loop */
+    double algorithmic_bytes; /* algorithmic bytes of the BP runs (bytes per iteration x iterations) */
+} fastlbp_alarm_stats;
+
+/* The user-feedback loop of BINGO with a simulated user who knows the answers: each round runs
+ * belief propagation (as fastlbp_run with max_iters, tol, damping, the current schedule, warm from
+ * the messages the previous round left), picks the uninspected alarm with the highest marginal
+ * P(x = 1), the value fastlbp_marginals would report (ties: the lowest position in alarm_vars; a
+ * device reduction over beliefs rebuilt from the messages), asks
+ * the user (labels) and clamps the alarm's variable to the answer. The loop ends once every true
+ * alarm has been inspected or after max_rounds rounds.
+ *   alarm_vars [A]   variables of the alarms, distinct, in [0, V)
+ *   labels [A]       the user's answer per alarm: 1 = true alarm, 0 = false alarm
+ *   out_order [max_rounds]  receives the positions (in alarm_vars) in inspection order
+ *   out_prob [max_rounds]   receives each picked alarm's marginal at the time of the pick (NULL ok)
+ * The clamps stay on the handle's evidence afterwards (fastlbp_evidence_clear releases them), and
+ * clamps set before the call stay too. stats may be NULL. Inversion count, Rank-100%-T and
+ * Rank-90%-T follow from out_order and labels. Errors: E_INVALID_ARG (bad sizes, a variable out of
+ * range or repeated, a label outside {0, 1}), E_OOM, E_DEVICE. */
+int fastlbp_alarm_loop(fastlbp_graph_t g, int32_t num_alarms, const int32_t *alarm_vars, const int8_t *labels,
+                       int32_t max_rounds, int32_t max_iters, double tol, double damping, int32_t *out_order,
+                       double *out_prob, fastlbp_alarm_stats *stats);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Serving: continuous batching of queries (the interactive loop of Section 5.2.2 at scale)      */

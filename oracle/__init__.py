@@ -9,6 +9,8 @@ Contents
                             and Definition 2, executed class by class without dependency analysis.
   * ``factor_messages``     Eq.(2) per factor type by disjoint-cube sums (C).
   * ``terms_messages``      Eq.(4) for a factor given as weighted terms (C, plain sums).
+  * ``alarm_loop``          BINGO's interactive alarm-ranking loop (Section 5.2.2, Section 5.3) with a
+                            simulated user, one ``bp_pairs`` run per round.
   * ``factor_sample``       one flooding update of a sample of factors from a given state, factor by
                             factor (C): the arithmetic of one ``bp`` iteration, for graphs too large
                             for whole iterations.
@@ -204,3 +206,36 @@ def factor_sample(w, msg1, factors, evidence="auto"):
     if rc != 0:
         raise RuntimeError("oracle_factor_sample: a sampled factor is out of range or a PRIOR")
     return edges, out1, contra.astype(bool)
+
+
+def alarm_loop(w, alarm_vars, labels, max_rounds=None, max_iters=500, tol=1e-6, damping=0.0, ranks=None,
+               follow=None):
+    """BINGO's interactive loop with a simulated user (Section 5.2.2): each round runs ``bp_pairs``
+    from the messages the previous round left (uniform at first) with the clamps so far, picks the
+    uninspected alarm with the highest marginal (the lowest position on ties), or follow[r] when
+    `follow` is given, and clamps its variable to its label. Stops once every true alarm has been
+    inspected, or after max_rounds rounds.
+    Returns (order [rounds], each pick's marginal [rounds], alarm marginals of every round [rounds][A])."""
+    alarm_vars = np.asarray(alarm_vars, dtype=np.int64)
+    labels = np.asarray(labels, dtype=np.int64)
+    A = len(alarm_vars)
+    ev = np.full(w.num_vars, -1, np.int8) if w.evidence is None else np.array(w.evidence, dtype=np.int8, copy=True)
+    m1 = np.full(w.num_edges, 0.5)
+    m0 = 1.0 - m1
+    inspected = np.zeros(A, dtype=bool)
+    total, found = int(labels.sum()), 0
+    order, probs, seen = [], [], []
+    n = A if max_rounds is None else int(max_rounds)
+    for r in range(n):
+        if found >= total or inspected.all():
+            break
+        marg, m0, m1, _ = bp_pairs(w, m0, m1, max_iters, tol, damping, ranks=ranks, evidence=ev)
+        pa = marg[alarm_vars]
+        seen.append(pa.copy())
+        pick = int(np.argmax(np.where(inspected, -1.0, pa))) if follow is None else int(follow[r])
+        order.append(pick)
+        probs.append(pa[pick])
+        inspected[pick] = True
+        ev[alarm_vars[pick]] = labels[pick]
+        found += int(labels[pick])
+    return np.array(order, dtype=np.int32), np.array(probs), np.array(seen).reshape(len(seen), A)

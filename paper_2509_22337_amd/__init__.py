@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libfastlbp.so")
 OK, E_INVALID_ARG, E_BAD_GRAPH, E_BAD_SCHEDULE, E_OOM, E_DEVICE, E_TOO_LARGE, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 SCHED_FLOODING, SCHED_RANKED = 0, 1
-EXEC_AUTO, EXEC_LEVELS, EXEC_PERSISTENT = 0, 1, 2
+EXEC_AUTO, EXEC_LEVELS, EXEC_PERSISTENT, EXEC_HYBRID = 0, 1, 2, 3
 MAX_DEGREE = 16385
 
 _ERR_NAMES = {E_INVALID_ARG: "E_INVALID_ARG", E_BAD_GRAPH: "E_BAD_GRAPH", E_BAD_SCHEDULE: "E_BAD_SCHEDULE",
@@ -71,6 +71,15 @@ class RunStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class AlarmStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("true_found", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("message_updates", ctypes.c_int64), ("device_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("algorithmic_bytes", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTS = [
     "fastlbp_options_default", "fastlbp_graph_create", "fastlbp_graph_create_terms", "fastlbp_graph_clone",
     "fastlbp_graph_destroy",
@@ -79,7 +88,7 @@ EXPORTS = [
     "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
     "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version", "fastlbp_server_options_default",
     "fastlbp_server_create", "fastlbp_server_submit", "fastlbp_server_poll", "fastlbp_server_wait",
-    "fastlbp_server_get_stats", "fastlbp_server_destroy",
+    "fastlbp_server_get_stats", "fastlbp_server_destroy", "fastlbp_alarm_loop",
 ]
 
 _lib = None
@@ -120,6 +129,7 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_evidence_clear.argtypes = [P]
     lib.fastlbp_run.argtypes = [P, i32, f64, f64, ctypes.POINTER(RunStats)]
     lib.fastlbp_marginals.argtypes = [P, P]
+    lib.fastlbp_alarm_loop.argtypes = [P, i32, P, P, i32, i32, f64, f64, P, P, ctypes.POINTER(AlarmStats)]
     lib.fastlbp_messages_get.argtypes = [P, P]
     lib.fastlbp_messages_set.argtypes = [P, P]
     lib.fastlbp_messages_reset.argtypes = [P]
@@ -259,7 +269,8 @@ class Graph:
         o = Options()
         lib.fastlbp_options_default(ctypes.byref(o))
         o.precision = {"fp64": FP64, "fp32": FP32}[precision]
-        o.executor = {"auto": EXEC_AUTO, "levels": EXEC_LEVELS, "persistent": EXEC_PERSISTENT}[executor]
+        o.executor = {"auto": EXEC_AUTO, "levels": EXEC_LEVELS, "persistent": EXEC_PERSISTENT,
+                      "hybrid": EXEC_HYBRID}[executor]
         o.device = int(device)
         o.use_graph = 1 if use_graph else 0
         self._keep = []
@@ -396,6 +407,42 @@ class Graph:
 
     def messages_reset(self):
         _check(load().fastlbp_messages_reset(self._h))
+
+    def alarm_loop(self, alarm_vars, labels, max_rounds=None, max_iters=500, tol=1e-6, damping=0.0):
+        """BINGO's interactive loop with a simulated user (fastlbp_alarm_loop): returns the
+        inspection order (positions in alarm_vars), each pick's marginal and the loop's stats."""
+        av = np.ascontiguousarray(alarm_vars, dtype=np.int32)
+        lb = np.ascontiguousarray(labels, dtype=np.int8)
+        if len(av) != len(lb):
+            raise FastLBPError(E_INVALID_ARG, "one label per alarm")
+        n = len(av) if max_rounds is None else int(max_rounds)
+        order = np.zeros(max(n, 1), dtype=np.int32)
+        prob = np.zeros(max(n, 1))
+        st = AlarmStats()
+        _check(load().fastlbp_alarm_loop(self._h, len(av), _p(av), _p(lb), n, int(max_iters), float(tol),
+                                         float(damping), _p(order), _p(prob), ctypes.byref(st)))
+        r = st.rounds
+        return order[:r].copy(), prob[:r].copy(), st.as_dict()
+
+
+def inversion_count(labels_in_order) -> int:
+    """Pairs of inspected alarms where a false alarm comes before a true one (Section 5.3):
+    the sum over false alarms of the true alarms inspected after them."""
+    l = np.asarray(labels_in_order, dtype=np.int64)
+    true_after = np.cumsum(l[::-1])[::-1] - l  # true alarms strictly after each position
+    return int(((1 - l) * true_after).sum())
+
+
+def rank_of_fraction(labels_in_order, frac: float, total_true: Optional[int] = None) -> int:
+    """Interactions needed to find at least ceil(frac x total_true) true alarms (Rank-100%-T for
+    frac = 1, Rank-90%-T for 0.9); -1 if the sequence does not reach that many."""
+    l = np.asarray(labels_in_order, dtype=np.int64)
+    total = int(l.sum()) if total_true is None else int(total_true)
+    need = int(np.ceil(frac * total - 1e-9))
+    if need <= 0:
+        return 0
+    hit = np.flatnonzero(np.cumsum(l) >= need)
+    return int(hit[0]) + 1 if len(hit) else -1
 
 
 class Server:

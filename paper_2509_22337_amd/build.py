@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfastlbp.so")
-SOURCES = ["runtime.hip", "host_graph.cpp", "server.cpp"]
+SOURCES = ["runtime.hip", "alarms.hip", "host_graph.cpp", "server.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

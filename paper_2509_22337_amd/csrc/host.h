@@ -78,6 +78,13 @@ struct HostPlan {
     std::vector<int32_t> level_lds;
     std::vector<int32_t> prec;
     int32_t stage_slots = 0;
+    // fused segments of the HYBRID executor: seg_end[L] > L when level L starts a run of narrow
+    // levels [L, seg_end[L]) executed by one workgroup (seg_teams[L]: the run has wavefront tasks)
+    std::vector<int32_t> seg_end;
+    std::vector<uint8_t> seg_teams;
+    int32_t fused_levels = 0;      // levels inside fused segments
+    int32_t launches_levels = 0;   // kernel launches of one LEVELS iteration
+    int32_t launches_hybrid = 0;   // kernel launches of one HYBRID iteration
     double bytes_per_iter = 0.0;   // algorithmic bytes of one iteration
     int64_t updates_per_iter = 0;  // non-PRIOR edges written per iteration
 

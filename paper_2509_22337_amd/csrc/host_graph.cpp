@@ -667,6 +667,47 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         level_lds[L] = ok ? 1 : 0;
         if (ok) stage_slots = std::max(stage_slots, slots);
     }
+    // narrow levels and the fused segments of the HYBRID executor; launches per iteration
+    seg_end.assign(exec_levels, -1);
+    seg_teams.assign(exec_levels, 0);
+    fused_levels = 0;
+    launches_levels = launches_hybrid = 1;  // the end-of-iteration kernel
+    auto cnt = [](const std::vector<int32_t> &off, int32_t L) { return off[L + 1] - off[L]; };
+    std::vector<uint8_t> narrow(exec_levels, 0);
+    for (int32_t L = 0; L < exec_levels; ++L) {
+        int launches = 0;
+        for (int b = 0; b < FB_COUNT; ++b) launches += cnt(fac_lvl_off[b], L) > 0 && b != FB_THREAD ? 1 : 0;
+        launches += cnt(frec_off, L) > 0 ? 1 : 0;
+        launches += cnt(vrec_off, L) > 0 ? 1 : 0;
+        launches += cnt(var_lvl_off[VB_WAVE], L) > 0 ? 1 : 0;
+        launches_levels += launches;
+        narrow[L] = cnt(frec_off, L) <= kFuseMaxRecs && cnt(vrec_off, L) <= kFuseMaxRecs &&
+                    cnt(fac_lvl_off[FB_TERMS_THREAD], L) <= kFuseMaxRecs && cnt(fac_lvl_off[FB_BLOCK], L) == 0 &&
+                    cnt(fac_lvl_off[FB_WAVE], L) + cnt(fac_lvl_off[FB_TERMS_WAVE], L) +
+                            cnt(var_lvl_off[VB_WAVE], L) <= kFuseMaxWaveTasks;
+    }
+    for (int32_t L = 0; L < exec_levels;) {
+        if (!narrow[L]) {
+            int launches = 0;
+            for (int b = 0; b < FB_COUNT; ++b) launches += cnt(fac_lvl_off[b], L) > 0 && b != FB_THREAD ? 1 : 0;
+            launches += (cnt(frec_off, L) > 0) + (cnt(vrec_off, L) > 0) + (cnt(var_lvl_off[VB_WAVE], L) > 0);
+            launches_hybrid += launches;
+            ++L;
+            continue;
+        }
+        int32_t e = L;
+        bool teams = false;
+        while (e < exec_levels && narrow[e]) {
+            teams = teams || cnt(fac_lvl_off[FB_WAVE], e) + cnt(fac_lvl_off[FB_TERMS_WAVE], e) +
+                                     cnt(fac_lvl_off[FB_TERMS_THREAD], e) + cnt(var_lvl_off[VB_WAVE], e) > 0;
+            ++e;
+        }
+        seg_end[L] = e;
+        seg_teams[L] = teams ? 1 : 0;
+        fused_levels += e - L;
+        launches_hybrid += 1;
+        L = e;
+    }
 }
 
 }  // namespace fastlbp

@@ -64,6 +64,9 @@ void step_levels_enqueue(fastlbp_graph *g, double damping, int32_t iters);
 float step_levels_finish(fastlbp_graph *g);
 const RunState &graph_host_state(fastlbp_graph *g);
 void marginals_into(fastlbp_graph *g, double *p1);
+// Rebuilds every belief from phi and the current messages (the executors may leave beliefs that
+// were updated incrementally during the last level), on the handle's stream, without waiting.
+void refresh_beliefs(fastlbp_graph *g);
 void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms);
 int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t *values);
 int graph_device(fastlbp_graph *g);
@@ -71,5 +74,8 @@ int graph_precision(fastlbp_graph *g);
 size_t graph_state_bytes(fastlbp_graph *g);
 int32_t graph_num_vars(fastlbp_graph *g);
 void graph_sync(fastlbp_graph *g);
+hipStream_t graph_stream(fastlbp_graph *g);
+const Belief *graph_beliefs(fastlbp_graph *g);
+const Alloc &graph_alloc(fastlbp_graph *g);
 
 }  // namespace fastlbp

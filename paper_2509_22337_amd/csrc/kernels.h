@@ -114,6 +114,14 @@ struct PolLin64 {
 // P(x = 1) of an LLR in bits, in float64 (used for the residual).
 __device__ __forceinline__ double prob1(double l) { return 1.0 / (1.0 + exp2(-l)); }
 
+// Marginal P(x = 1) of Eq.(3) from a belief; a belief with both infinite kinds (0/0) gives 1/2.
+__device__ __forceinline__ double belief_p1(const Belief &B) {
+    if (B.npos > 0 && B.nneg > 0) return 0.5;
+    if (B.npos > 0) return 1.0;
+    if (B.nneg > 0) return 0.0;
+    return 1.0 / (1.0 + exp2(-B.fin));
+}
+
 // Variable-to-factor message of Eq.(1) from the variable's belief minus the factor's own incoming
 // message. `null` marks the product of two exact zeros (0, 0).
 template <class P>

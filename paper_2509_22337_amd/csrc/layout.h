@@ -107,6 +107,10 @@ constexpr int kWaveMaxDeg = 257;     // one wavefront per factor: 64 lanes x up 
 constexpr int kBlockMaxDeg = 16385;  // one 1024-thread workgroup per factor: 1024 x 16 + head
 constexpr int kVarThreadMaxDeg = 64; // one thread per variable, else one wavefront
 constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record (VarRec::e)
+// A level is narrow (one workgroup runs it in the HYBRID executor) with at most this many factor
+// records and variable records, no workgroup-per-factor task and few wavefront tasks.
+constexpr int kFuseMaxRecs = 2048;
+constexpr int kFuseMaxWaveTasks = 128;
 
 // Factors given as weighted terms: FB_TERMS_THREAD one thread per factor (degree <= kThreadMaxDeg),
 // FB_TERMS_WAVE one wavefront per factor (degree up to 64)

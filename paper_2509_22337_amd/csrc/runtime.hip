@@ -200,17 +200,7 @@ __global__ void k_finalize(RunState *st) {
 __global__ void k_marginals(const Belief *bel, int32_t V, double *out) {
     int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    Belief B = bel[v];
-    double p;
-    if (B.npos > 0 && B.nneg > 0)
-        p = 0.5;
-    else if (B.npos > 0)
-        p = 1.0;
-    else if (B.nneg > 0)
-        p = 0.0;
-    else
-        p = 1.0 / (1.0 + exp2(-B.fin));
-    out[v] = p;
+    out[v] = belief_p1(bel[v]);
 }
 
 // Descriptor of one run for the persistent executor: the graph view (structure + state pointers,
@@ -225,13 +215,106 @@ struct RunDesc {
     int32_t step;          // > 0: this launch stops the run after `step` more iterations
 };
 
-// One workgroup of NT threads runs every level and iteration of one run, with workgroup barriers
-// between phases. Used when the levels are too narrow to fill the GPU. Thread tasks come as records
-// whose loads are issued one phase ahead (the variable records of a level while its factor phase
-// runs, the factor records of the next level while the variable phase runs), so each phase waits
-// for one round of dependent loads. TEAMS adds the wavefront- and workgroup-per-factor paths
-// (plans with factors of degree > 8). A launch returns when the run is done or its iteration
-// count reaches st->step_end, so a caller can advance many runs in steps.
+// Levels [L0, L1) of one run in one workgroup of NT threads, with workgroup barriers between
+// phases. Thread tasks come as records whose loads are issued one phase ahead (the variable records
+// of a level while its factor phase runs, the factor records of the next level while the variable
+// phase runs), so each phase waits for one round of dependent loads. On entry `fr` / `pr` hold this
+// thread's first factor record of L0 and, if L0 is staged, its first staged variable record; on
+// exit they hold those of level `Lnext` (none when Lnext < 0). TEAMS adds the wavefront- and
+// workgroup-per-factor paths and the weighted-term paths. foff / voff / staged give each level's
+// record offsets and staging flag.
+template <class P, bool DAMP, bool TEAMS, int NT, class FOff, class VOff, class Staged>
+__device__ __forceinline__ void level_range(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
+                                            int32_t L0, int32_t L1, int32_t Lnext, FOff foff, VOff voff,
+                                            Staged staged, typename P::S *s_slot, TeamLds<typename P::V> *lds,
+                                            Acc &acc, FacRec &fr, VarRecP &pr) {
+    using S = typename P::S;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const GPtr<const FacRec> frec = plan.frec;
+    const GPtr<const VarRec> vrec = plan.vrec;
+    const GPtr<const VarRecP> prec = plan.prec;
+    for (int32_t L = L0; L < L1; ++L) {
+        const int32_t f0 = foff(L), f1 = foff(L + 1);
+        const int32_t v0 = voff(L), v1 = voff(L + 1);
+        const bool stg = staged(L);
+        // variable phase inputs, issued now: a staged level needs each variable's belief
+        // before the level; an unstaged one its record
+        VarRec vr = {};
+        Belief bold = {0.0, 0, 0};
+        const VarRecP pc = pr;
+        if (v0 + tid < v1) {
+            if (stg)
+                bold = g.bel.ld(pc.v);
+            else
+                vr = vrec.ld_stream(v0 + tid);
+        }
+        S *const slots = stg ? s_slot : nullptr;
+        if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots);
+        for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots);
+        if (TEAMS) {
+            const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
+            int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
+            for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
+        }
+        if (TEAMS) {
+            const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_THREAD];
+            int32_t o0 = plan.fac_lvl_off[FB_TERMS_THREAD][L], o1 = plan.fac_lvl_off[FB_TERMS_THREAD][L + 1];
+            for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_thread<P, false, DAMP>(g, lst[i], L, acc);
+        }
+        if (TEAMS) {
+            const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_WAVE];
+            int32_t o0 = plan.fac_lvl_off[FB_TERMS_WAVE][L], o1 = plan.fac_lvl_off[FB_TERMS_WAVE][L + 1];
+            for (int32_t i = o0 + w; i < o1; i += NW) factor_terms<P, false, DAMP>(g, lst[i], lane, L, acc);
+        }
+        if (TEAMS) {
+            const GPtr<const int32_t> lst = plan.fac_list[FB_BLOCK];
+            int32_t o0 = plan.fac_lvl_off[FB_BLOCK][L], o1 = plan.fac_lvl_off[FB_BLOCK][L + 1];
+            for (int32_t i = o0; i < o1; ++i)
+                factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, lds);
+        }
+        if (stg) {
+            // the variable phase reads only the staging slots and beliefs loaded before the
+            // level: wait for LDS, not for the messages' global stores
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        } else {
+            __syncthreads();
+        }
+        {
+            // records of the next level (Lnext after the last level of the range)
+            const int32_t Ln = (L + 1 < L1) ? L + 1 : Lnext;
+            fr = FacRec{};
+            pr = VarRecP{};
+            if (Ln >= 0) {
+                const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
+                if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
+                const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
+                if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
+            }
+        }
+        if (stg) {
+            if (v0 + tid < v1) var_staged<P>(g, pc, bold, s_slot);
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) {
+                const VarRecP q = prec.ld_stream(i);
+                var_staged<P>(g, q, g.bel.ld(q.v), s_slot);
+            }
+        } else {
+            if (v0 + tid < v1) var_rec<P>(g, vr);
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
+            const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
+            int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
+            for (int32_t i = o0 + w; i < o1; i += NW) var_wave<P>(g, lst[i], lane);
+        }
+        // the next level reads these beliefs and messages from memory
+        __syncthreads();
+    }
+}
+
+// One workgroup of NT threads runs every level and iteration of one run. Used when the levels are
+// too narrow to fill the GPU. A launch returns when the run is done or its iteration count reaches
+// st->step_end, so a caller can advance many runs in steps.
 template <class P, bool DAMP, bool TEAMS, int NT>
 __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int32_t lds_levels, int32_t stage_cap) {
     using S = typename P::S;
@@ -252,7 +335,6 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     GPtr<RunState> st = D.st;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const GPtr<const FacRec> frec = plan.frec;
-    const GPtr<const VarRec> vrec = plan.vrec;
     const GPtr<const VarRecP> prec = plan.prec;
     const int32_t NL = plan.num_levels;
     // staged levels need the launch's slot area to hold this plan's largest staged level
@@ -285,80 +367,7 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     if (NL > 0 && staged(0) && voff(0) + tid < voff(1)) pr = prec.ld_stream(voff(0) + tid);
     while (!s_done) {
         Acc acc = {0.0, 0u};
-        for (int32_t L = 0; L < NL; ++L) {
-            const int32_t f0 = foff(L), f1 = foff(L + 1);
-            const int32_t v0 = voff(L), v1 = voff(L + 1);
-            const bool stg = staged(L);
-            // variable phase inputs, issued now: a staged level needs each variable's belief
-            // before the level; an unstaged one its record
-            VarRec vr = {};
-            Belief bold = {0.0, 0, 0};
-            const VarRecP pc = pr;
-            if (v0 + tid < v1) {
-                if (stg)
-                    bold = g.bel.ld(pc.v);
-                else
-                    vr = vrec.ld_stream(v0 + tid);
-            }
-            S *const slots = stg ? s_slot : nullptr;
-            if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots);
-            for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots);
-            if (TEAMS) {
-                const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
-                int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
-                for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
-            }
-            if (TEAMS) {
-                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_THREAD];
-                int32_t o0 = plan.fac_lvl_off[FB_TERMS_THREAD][L], o1 = plan.fac_lvl_off[FB_TERMS_THREAD][L + 1];
-                for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_thread<P, false, DAMP>(g, lst[i], L, acc);
-            }
-            if (TEAMS) {
-                const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_WAVE];
-                int32_t o0 = plan.fac_lvl_off[FB_TERMS_WAVE][L], o1 = plan.fac_lvl_off[FB_TERMS_WAVE][L + 1];
-                for (int32_t i = o0 + w; i < o1; i += NW) factor_terms<P, false, DAMP>(g, lst[i], lane, L, acc);
-            }
-            if (TEAMS) {
-                const GPtr<const int32_t> lst = plan.fac_list[FB_BLOCK];
-                int32_t o0 = plan.fac_lvl_off[FB_BLOCK][L], o1 = plan.fac_lvl_off[FB_BLOCK][L + 1];
-                for (int32_t i = o0; i < o1; ++i)
-                    factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, &lds);
-            }
-            if (stg) {
-                // the variable phase reads only the staging slots and beliefs loaded before the
-                // level: wait for LDS, not for the messages' global stores
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                __builtin_amdgcn_s_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-            } else {
-                __syncthreads();
-            }
-            {
-                // records of the next level (level 0 of the next iteration after the last)
-                const int32_t Ln = (L + 1 < NL) ? L + 1 : 0;
-                const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
-                fr = FacRec{};
-                if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
-                pr = VarRecP{};
-                const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
-            }
-            if (stg) {
-                if (v0 + tid < v1) var_staged<P>(g, pc, bold, s_slot);
-                for (int32_t i = v0 + tid + NT; i < v1; i += NT) {
-                    const VarRecP q = prec.ld_stream(i);
-                    var_staged<P>(g, q, g.bel.ld(q.v), s_slot);
-                }
-            } else {
-                if (v0 + tid < v1) var_rec<P>(g, vr);
-                for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
-                const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
-                int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
-                for (int32_t i = o0 + w; i < o1; i += NW) var_wave<P>(g, lst[i], lane);
-            }
-            // the next level reads these beliefs and messages from memory
-            __syncthreads();
-        }
+        level_range<P, DAMP, TEAMS, NT>(g, plan, 0, NL, 0, foff, voff, staged, s_slot, &lds, acc, fr, pr);
         // end of iteration: block-wide residual and contradiction count
         double r = acc.r;
         unsigned int c = acc.contra;
@@ -397,6 +406,32 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
         const __attribute__((address_space(1))) int32_t *src = (const __attribute__((address_space(1))) int32_t *)st.get();
         for (int k = 0; k < int(kRunStateHeader / 4); ++k) D.status[k] = src[k];
     }
+}
+
+// Levels [L0, L1) of one iteration of the LEVELS executor in one workgroup: a run of narrow
+// levels that would otherwise cost a few launches each. The residual and contradiction count go
+// into the run state's slots like those of the other factor kernels.
+template <class P, bool DAMP, bool TEAMS, int NT>
+__global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typename P::V> g, DevPlan plan,
+                                                     RunState *st, int32_t L0, int32_t L1, int32_t stage_cap) {
+    using S = typename P::S;
+    using V = typename P::V;
+    __shared__ TeamLds<V> lds;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    if (st->done) return;
+    S *const s_slot = (S *)s_dyn;
+    const int tid = threadIdx.x;
+    const bool staging = plan.stage_slots > 0 && plan.stage_slots <= stage_cap;
+    auto foff = [&](int32_t L) { return (int32_t)plan.frec_off[L]; };
+    auto voff = [&](int32_t L) { return (int32_t)plan.vrec_off[L]; };
+    auto staged = [&](int32_t L) { return staging && plan.level_lds[L] != 0; };
+    FacRec fr = {};
+    VarRecP pr = {};
+    if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld_stream(foff(L0) + tid);
+    if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr = plan.prec.ld_stream(voff(L0) + tid);
+    Acc acc = {0.0, 0u};
+    level_range<P, DAMP, TEAMS, NT>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, &lds, acc, fr, pr);
+    flush_acc<NT>(acc, st);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -575,6 +610,7 @@ struct fastlbp_graph {
     hipGraph_t graph = nullptr;
     int graph_iters = 0;
     double graph_damping = -1.0;
+    bool graph_fused = false;
     const Plan *graph_plan = nullptr;
     fastlbp_run_stats last{};
 
@@ -782,13 +818,41 @@ static void launch_init_beliefs(fastlbp_graph *g, const DevGraph<typename PP::S,
     HIPCHK(hipGetLastError());
 }
 
+static int persistent_threads(int precision, bool teams, int runs);
+
+// One launch of k_levels_fused for levels [L0, L1).
+template <class PP, bool DAMP>
+static void launch_fused(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, const DevPlan &dp,
+                         int32_t L0, int32_t L1, bool teams, hipStream_t s) {
+    const int32_t cap = g->P->hp.stage_slots;
+    const size_t lds = sizeof(typename PP::S) * 2 * size_t(std::max(cap, 1));
+    const int nt = persistent_threads(g->precision(), teams, 1);
+    if constexpr (std::is_same<PP, PolLog32>::value) {
+        if (nt == 1024) {
+            k_levels_fused<PP, DAMP, false, 1024><<<1, 1024, lds, s>>>(dg, dp, g->st, L0, L1, cap);
+            return;
+        }
+    }
+    if (teams)
+        k_levels_fused<PP, DAMP, true, 512><<<1, 512, lds, s>>>(dg, dp, g->st, L0, L1, cap);
+    else
+        k_levels_fused<PP, DAMP, false, 512><<<1, 512, lds, s>>>(dg, dp, g->st, L0, L1, cap);
+}
+
 // One iteration of the LEVELS executor: for every level, the factor phase then the variable phase.
+// fuse (HYBRID executor): each run of narrow levels goes to one single-workgroup launch.
 template <class PP, bool ALL, bool DAMP>
-static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg) {
+static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, bool fuse) {
     const HostPlan &pl = g->P->hp;
     const Plan &P = *g->P;
     hipStream_t s = g->L.stream;
+    const DevPlan dp = P.view();
     for (int32_t L = 0; L < pl.exec_levels; ++L) {
+        if (fuse && pl.seg_end[L] > L) {
+            launch_fused<PP, DAMP>(g, dg, dp, L, pl.seg_end[L], pl.seg_teams[L] != 0, s);
+            L = pl.seg_end[L] - 1;
+            continue;
+        }
         int32_t o, n;
         o = pl.frec_off[L];
         n = pl.frec_off[L + 1] - o;
@@ -830,30 +894,38 @@ static int persistent_threads(int precision, bool teams, int runs) {
 
 static int choose_executor(const fastlbp_graph *g) {
     int ex = g->opts.executor;
-    if (ex == FASTLBP_EXEC_LEVELS || ex == FASTLBP_EXEC_PERSISTENT) return ex;
-    // one workgroup keeps up with a level of a few thousand edges; wider levels need the GPU
-    if (g->P->hp.max_level_edges <= 8192 && g->hg().nonprior_edges <= (int64_t(4) << 20)) return FASTLBP_EXEC_PERSISTENT;
+    if (ex != FASTLBP_EXEC_AUTO) return ex;
+    // one workgroup keeps up with a level of a few thousand edges; wider levels need the GPU.
+    // A plan with a few wide levels among many narrow ones runs the narrow ones fused.
+    const HostPlan &hp = g->P->hp;
+    const bool small = g->hg().nonprior_edges <= (int64_t(4) << 20);
+    if (small && hp.fused_levels == hp.exec_levels) return FASTLBP_EXEC_PERSISTENT;  // every level narrow
+    if (hp.fused_levels >= 4 && hp.launches_hybrid * 2 <= hp.launches_levels) return FASTLBP_EXEC_HYBRID;
+    if (small && hp.max_level_edges <= 8192) return FASTLBP_EXEC_PERSISTENT;
     return FASTLBP_EXEC_LEVELS;
 }
 
 // The handle's hipGraph of K captured iterations, re-captured when K, damping or the plan changed.
 template <class PP, bool ALL, bool DAMP>
 static void ensure_iteration_graph(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, int K,
-                                   double damping) {
-    if (g->gexec && g->graph_iters == K && g->graph_damping == damping && g->graph_plan == g->P.get()) return;
+                                   double damping, bool fuse) {
+    if (g->gexec && g->graph_iters == K && g->graph_damping == damping && g->graph_plan == g->P.get() &&
+        g->graph_fused == fuse)
+        return;
     g->drop_graph();
     hipStream_t s = g->L.stream;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+    for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg, fuse);
     HIPCHK(hipStreamEndCapture(s, &g->graph));
     HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
     g->graph_iters = K;
     g->graph_damping = damping;
     g->graph_plan = g->P.get();
+    g->graph_fused = fuse;
 }
 
 template <class PP, bool ALL, bool DAMP>
-static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping) {
+static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse) {
     auto dg = g->view<PP>(damping);
     hipStream_t s = g->L.stream;
     k_run_init<<<1, 64, 0, s>>>(g->st, max_iters, tol);
@@ -862,17 +934,17 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
     if (max_iters <= 0) return;
     // iterations per replay: enough to amortise the launch, few enough to stop soon after
     // convergence (kernels of finished iterations return at once)
-    int per_iter_kernels = 1 + 2 * std::max(1, g->P->hp.exec_levels);
+    int per_iter_kernels = std::max(1, fuse ? g->P->hp.launches_hybrid : g->P->hp.launches_levels);
     int K = std::max(1, std::min(32, 2048 / per_iter_kernels));
     K = std::min(K, max_iters);
     bool use_graph = g->opts.use_graph != 0;
-    if (use_graph) ensure_iteration_graph<PP, ALL, DAMP>(g, dg, K, damping);
+    if (use_graph) ensure_iteration_graph<PP, ALL, DAMP>(g, dg, K, damping, fuse);
     int done_iters = 0;
     while (true) {
         if (use_graph)
             HIPCHK(hipGraphLaunch(g->gexec, s));
         else
-            for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+            for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg, fuse);
         HIPCHK(hipGetLastError());
         done_iters += K;
         if (done_iters >= max_iters) break;
@@ -968,8 +1040,8 @@ __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int
 
 template <class PP, bool ALL, bool DAMP>
 static void run_single(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec) {
-    if (exec == FASTLBP_EXEC_LEVELS) {
-        run_levels<PP, ALL, DAMP>(g, max_iters, tol, damping);
+    if (exec == FASTLBP_EXEC_LEVELS || exec == FASTLBP_EXEC_HYBRID) {
+        run_levels<PP, ALL, DAMP>(g, max_iters, tol, damping, exec == FASTLBP_EXEC_HYBRID);
         return;
     }
     k_run_init_step<<<1, 64, 0, g->L.stream>>>(g->st, max_iters, tol, max_iters);
@@ -1030,11 +1102,12 @@ static void step_levels_t(fastlbp_graph *g, double damping, int32_t iters) {
     hipStream_t s = g->L.stream;
     HIPCHK(hipEventRecord(g->L.k0, s));
     launch_init_beliefs<PP>(g, dg);
+    const bool fuse = choose_executor(g) == FASTLBP_EXEC_HYBRID;
     if (g->opts.use_graph) {
-        ensure_iteration_graph<PP, ALL, DAMP>(g, dg, iters, damping);
+        ensure_iteration_graph<PP, ALL, DAMP>(g, dg, iters, damping, fuse);
         HIPCHK(hipGraphLaunch(g->gexec, s));
     } else {
-        for (int k = 0; k < iters; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg);
+        for (int k = 0; k < iters; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg, fuse);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(g->L.k1, s));
@@ -1049,7 +1122,7 @@ static void step_levels_p(fastlbp_graph *g, double damping, int32_t iters) {
     if (!all && !damp) step_levels_t<PP, false, false>(g, damping, iters);
 }
 
-bool graph_wide(fastlbp_graph *g) { return choose_executor(g) == FASTLBP_EXEC_LEVELS; }
+bool graph_wide(fastlbp_graph *g) { return choose_executor(g) != FASTLBP_EXEC_PERSISTENT; }
 
 void step_levels_enqueue(fastlbp_graph *g, double damping, int32_t iters) {
     if (g->precision() == FASTLBP_FP32)
@@ -1070,12 +1143,17 @@ void read_state(fastlbp_graph *g, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
 }
 
-void marginals_into(fastlbp_graph *g, double *p1) {
+void refresh_beliefs(fastlbp_graph *g) {
     if (g->hg().V == 0) return;
     if (g->precision() == FASTLBP_FP32)
         launch_init_beliefs<PolLog32>(g, g->view<PolLog32>(0.0));
     else
         launch_init_beliefs<PolLin64>(g, g->view<PolLin64>(0.0));
+}
+
+void marginals_into(fastlbp_graph *g, double *p1) {
+    if (g->hg().V == 0) return;
+    refresh_beliefs(g);
     k_marginals<<<grid_for(g->hg().V, 256), 256, 0, g->L.stream>>>(g->bel, g->hg().V, g->marg);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(p1, g->marg, sizeof(double) * g->hg().V, hipMemcpyDeviceToHost, g->L.stream));
@@ -1122,6 +1200,9 @@ size_t graph_state_bytes(fastlbp_graph *g) { return g->state_bytes(); }
 int32_t graph_num_vars(fastlbp_graph *g) { return g->hg().V; }
 const RunState &graph_host_state(fastlbp_graph *g) { return *g->h_state; }
 void graph_sync(fastlbp_graph *g) { HIPCHK(hipStreamSynchronize(g->L.stream)); }
+hipStream_t graph_stream(fastlbp_graph *g) { return g->L.stream; }
+const Belief *graph_beliefs(fastlbp_graph *g) { return g->bel; }
+const Alloc &graph_alloc(fastlbp_graph *g) { return g->alloc; }
 
 }  // namespace fastlbp
 
@@ -1148,7 +1229,7 @@ static int check_options(const fastlbp_options &o) {
         set_error("precision must be FASTLBP_FP64 or FASTLBP_FP32");
         return FASTLBP_E_INVALID_ARG;
     }
-    if (o.executor < FASTLBP_EXEC_AUTO || o.executor > FASTLBP_EXEC_PERSISTENT) {
+    if (o.executor < FASTLBP_EXEC_AUTO || o.executor > FASTLBP_EXEC_HYBRID) {
         set_error("unknown executor");
         return FASTLBP_E_INVALID_ARG;
     }

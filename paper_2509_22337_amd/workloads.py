@@ -653,6 +653,86 @@ def random_terms(seed: int, num_vars: int = 40, num_factors: int = 50, max_arity
     return w
 
 
+def alarm_graph(seed: int = 0, num_inputs: int = 8000, num_derived: int = 20000, max_rules: int = 3,
+                body=(1, 3), rule_p=(0.5, 0.95), input_p=(0.8, 0.99), num_alarms: int = 1000,
+                max_iters: int = 500, tol: float = 1e-6, damping: float = 0.0) -> Workload:
+    """A BINGO-style derivation graph with a ground truth for the alarm-ranking loop (Section
+    5.2.2). Tuples 0 .. num_inputs-1 are input facts, each with a PRIOR; every later tuple gets
+    1..max_rules rules whose bodies are 1-3 distinct lower tuples. A rule is a clause variable
+    AND(body, clause), and a tuple's rules meet in NOISY_OR(clauses..., tuple) with one
+    activation probability per rule (leak 0). The alarms are the last num_alarms tuples.
+
+    The ground truth is one world drawn from the same generative story, in topological order:
+    an input fact holds with its prior, a clause holds exactly when its body holds, and a tuple
+    holds when one of its holding clauses fires (each with its activation probability). An alarm
+    is true when its tuple holds in that world. Attributes added: ``alarms`` (variable ids),
+    ``labels`` (int8, 1 = true alarm) and ``world`` (int8 per variable)."""
+    rng = np.random.default_rng(seed)
+    T = num_inputs + num_derived
+    k = rng.integers(1, max_rules + 1, num_derived)
+    heads = np.repeat(np.arange(num_inputs, T, dtype=np.int64), k)
+    R = len(heads)
+    nb = body[1]
+    bsize = rng.integers(body[0], body[1] + 1, R)
+    bodies = (rng.random((R, nb)) * heads[:, None]).astype(np.int64)
+    mask = np.arange(nb)[None, :] < bsize[:, None]
+    for _ in range(200):
+        srt = np.sort(np.where(mask, bodies, -1 - np.arange(nb)[None, :]), axis=1)
+        bad = np.flatnonzero(((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] >= 0)).any(axis=1))
+        if len(bad) == 0:
+            break
+        bodies[bad] = (rng.random((len(bad), nb)) * heads[bad, None]).astype(np.int64)
+    p = rng.uniform(rule_p[0], rule_p[1], R)
+    pin = rng.uniform(input_p[0], input_p[1], num_inputs)
+    # ground truth, in topological order (bodies precede heads; rules are sorted by head)
+    fires = rng.random(R) < p
+    world = np.zeros(T + R, dtype=np.int8)
+    world[:num_inputs] = rng.random(num_inputs) < pin
+    for r in range(R):
+        c = bool(world[bodies[r, :bsize[r]]].all())
+        world[T + r] = c
+        if c and fires[r]:
+            world[heads[r]] = 1
+    nv = T + R
+    and_deg = bsize + 1
+    and_off = _csr(and_deg)
+    and_vars = np.empty(int(and_deg.sum()), dtype=np.int64)
+    for j in range(nb):
+        sel = bsize > j
+        and_vars[and_off[:-1][sel] + j] = bodies[sel, j]
+    and_vars[and_off[1:] - 1] = T + np.arange(R)
+    no_deg = k + 1
+    no_off = _csr(no_deg)
+    no_vars = np.empty(int(no_deg.sum()), dtype=np.int64)
+    no_ep = np.zeros(int(no_deg.sum()))
+    start = _csr(k)[:-1]
+    hidx = np.repeat(np.arange(num_derived), k)
+    dst = no_off[hidx] + (np.arange(R) - start[hidx])
+    no_vars[dst] = T + np.arange(R)
+    no_ep[dst] = p
+    no_vars[no_off[1:] - 1] = np.arange(num_inputs, T)
+    fac_type = np.concatenate([np.full(R, AND), np.full(num_derived, NOISY_OR),
+                               np.full(num_inputs, PRIOR)]).astype(np.uint8)
+    deg = np.concatenate([and_deg, no_deg, np.ones(num_inputs, dtype=np.int64)])
+    w = Workload(num_vars=nv, fac_off=_csr(deg),
+                 edge_var=np.concatenate([and_vars, no_vars, np.arange(num_inputs)]).astype(np.int32),
+                 fac_type=fac_type, fac_param=np.concatenate([np.zeros(R + num_derived), pin]),
+                 edge_param=np.concatenate([np.zeros(len(and_vars)), no_ep, np.zeros(num_inputs)]), edge_rank=None,
+                 evidence=np.full(nv, -1, dtype=np.int8), max_iters=max_iters, tol=tol, damping=damping,
+                 name="alarms")
+    w.alarms = np.arange(T - num_alarms, T, dtype=np.int32)
+    w.labels = world[w.alarms].astype(np.int8)
+    w.world = world
+    w.meta = dict(seed=seed, num_inputs=num_inputs, num_derived=num_derived, num_rules=R)
+    return w
+
+
+def seqfix_ranks(w: Workload) -> np.ndarray:
+    """The round-robin asynchronous strategy (SEQFIX, Section 4.2): every edge in its own class, in
+    edge order."""
+    return np.arange(w.num_edges, dtype=np.int32)
+
+
 def config(name: str, seed: int = 0, scale: float = 1.0) -> Workload:
     """The five benchmark configurations by short name (C1..C5); ``scale`` shrinks C2/C3/C5 for
     tests that must finish quickly."""
