@@ -73,6 +73,8 @@ struct HostPlan {
     // degree group padded to a multiple of 64 records; frec_off / vrec_off delimit the levels
     std::vector<int32_t> frec, vrec;
     std::vector<int32_t> frec_off, vrec_off;
+    // task records of the weighted-term thread bucket (12 int32 each, TermRec), per level
+    std::vector<int32_t> trec, trec_off;
     // levels whose new messages the persistent executor stages in LDS: flag per level, variable
     // tasks with staging slots (8 int32 each, in vrec's order), most slots of a staged level
     std::vector<int32_t> level_lds;

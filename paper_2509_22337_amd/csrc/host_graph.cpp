@@ -618,6 +618,25 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         }
         vrec_off.push_back(int32_t(vrec.size() / 8));
     }
+    // weighted-term records: {b, d | terms << 8 | written-edge mask << 16, first term, variables}
+    trec.clear();
+    trec_off.assign(1, 0);
+    for (int32_t L = 0; L < exec_levels; ++L) {
+        for (int32_t i = fac_lvl_off[FB_TERMS_THREAD][L]; i < fac_lvl_off[FB_TERMS_THREAD][L + 1]; ++i) {
+            const int32_t a = fac_list[FB_TERMS_THREAD][i];
+            const int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
+            int32_t r[12] = {0};
+            unsigned mask = 0;
+            for (int64_t k = 0; k < d; ++k)
+                if (edge_exec_level[b + k] == L) mask |= 1u << k;
+            r[0] = int32_t(b);
+            r[1] = int32_t(d) | ((g.term_off[a + 1] - g.term_off[a]) << 8) | int32_t(mask << 16);
+            r[2] = g.term_off[a];
+            for (int64_t k = 0; k < d; ++k) r[3 + k] = g.edge_var[b + k];
+            trec.insert(trec.end(), r, r + 12);
+        }
+        trec_off.push_back(int32_t(trec.size() / 12));
+    }
     // staging in LDS: a level qualifies when all of its written edges come from thread-bucket
     // factors, its variables have at most kStagedEdges written edges each and none takes the
     // wavefront path, and its written edges fit kMaxStageSlots

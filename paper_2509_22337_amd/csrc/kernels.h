@@ -574,19 +574,21 @@ __device__ __forceinline__ void factor_terms(const DevGraph<typename P::S, typen
         store_msg<P, DAMP>(g, b + lane, old, acc0, acc1, nnull - (nl ? 1 : 0) > 0, acc);
 }
 
-// Weighted-term factor of degree <= kThreadMaxDeg in one thread: for every term, a forward pass
-// gives the weight times the product over the edges before k and a backward pass the product over
-// the edges after k, so each term costs O(degree) and the factor O(terms x degree). Term t's
-// indicators come as the mask pair term_mask[t] (fixed edges, their values).
-template <class P, bool ALL_ACTIVE, bool DAMP>
-__device__ __forceinline__ void factor_terms_thread(const DevGraph<typename P::S, typename P::V> &g, int32_t a,
-                                                    int level, Acc &acc) {
+// Weighted-term factor of degree <= kThreadMaxDeg in one thread, from its task record: for every
+// term, a forward pass gives the weight times the product over the edges before k and a backward
+// pass the product over the edges after k, so each term costs O(degree) and the factor
+// O(terms x degree). Term t's indicators come as the mask pair term_mask[t] (fixed edges, their
+// values); the record's mask selects the edges the level writes.
+template <class P, bool DAMP>
+__device__ __forceinline__ void factor_terms_rec(const DevGraph<typename P::S, typename P::V> &g, const TermRec &r,
+                                                 Acc &acc) {
     using S = typename P::S;
     using V = typename P::V;
     constexpr int K = kThreadMaxDeg;
-    const int32_t b = g.fac_off[a];
-    const int32_t d = g.fac_off[a + 1] - b;
-    const int32_t t0 = g.term_off[a], t1 = g.term_off[a + 1];
+    const int32_t b = r.b;
+    const int32_t d = r.meta & 0xff;
+    const int32_t t0 = r.t0, t1 = r.t0 + ((r.meta >> 8) & 0xff);
+    const unsigned act = ((unsigned)r.meta >> 16) & 0xffu;
     S old[K];
     V m0[K], m1[K], a0[K], a1[K];
     bool nl[K];
@@ -601,7 +603,7 @@ __device__ __forceinline__ void factor_terms_thread(const DevGraph<typename P::S
         nl[k] = false;
         if (k < d) {
             old[k] = g.msg[b + k];
-            const S vf = v2f<P>(g.bel.ld(g.edge_var[b + k]), old[k], nl[k]);
+            const S vf = v2f<P>(g.bel.ld(r.u[k]), old[k], nl[k]);
             if (!nl[k]) P::leaf(vf, m0[k], m1[k]);
             nnull += nl[k] ? 1 : 0;
         }
@@ -629,7 +631,7 @@ __device__ __forceinline__ void factor_terms_thread(const DevGraph<typename P::S
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        if (k < d && is_active<ALL_ACTIVE>(g.edge_level, b + k, level))
+        if (k < d && ((act >> k) & 1u))
             store_msg<P, DAMP>(g, b + k, old[k], a0[k], a1[k], nnull - (nl[k] ? 1 : 0) > 0, acc);
 }
 

@@ -157,6 +157,14 @@ struct alignas(16) FacRec {
                    // record's written edges (persistent executor, levels staged in LDS)
 };
 
+// Task record of a weighted-term factor of degree <= 8 (thread path, both executors).
+struct alignas(16) TermRec {
+    int32_t b;     // first edge
+    int32_t meta;  // degree | term count << 8 | (edges the level writes, bit k = edge b + k) << 16
+    int32_t t0;    // first term
+    int32_t u[9];  // variable of edge b + k, k < degree; u[8] unused
+};
+
 struct alignas(16) VarRec {
     int32_t v, start, cnt;  // variable, first position in var_edge, degree | (padding record) << 30
     int32_t e[5];           // its first edges (the rest from var_edge)
@@ -192,6 +200,9 @@ struct DevPlan {
     // level's new messages from LDS (then prec holds its variable tasks, in vrec's order)
     GPtr<const VarRecP> prec;
     GPtr<const int32_t> level_lds;  // [num_levels]
+    // weighted-term factors of degree <= 8, per level (sorted by degree, then term count)
+    GPtr<const TermRec> trec;
+    GPtr<const int32_t> trec_off;   // [num_levels+1]
     int32_t stage_slots;            // most slots any staged level uses (0: none staged)
 };
 

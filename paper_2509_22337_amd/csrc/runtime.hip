@@ -90,15 +90,15 @@ __global__ __launch_bounds__(256) void k_fac_terms(DevGraph<typename P::S, typen
     flush_acc<256>(acc, st);
 }
 
-// Weighted-term factors of degree <= 8, one thread each.
-template <class P, bool ALL, bool DAMP>
-__global__ __launch_bounds__(256) void k_fac_terms_thread(DevGraph<typename P::S, typename P::V> g,
-                                                          const int32_t *list, int32_t count, int32_t level,
-                                                          RunState *st) {
+// Weighted-term factors of degree <= 8, one thread per task record.
+template <class P, bool DAMP>
+__global__ __launch_bounds__(256) void k_fac_terms_rec(DevGraph<typename P::S, typename P::V> g, const TermRec *recs,
+                                                       int32_t count, RunState *st) {
     if (st->done) return;
     Acc acc = {0.0, 0u};
+    const GPtr<const TermRec> R(recs);
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-        factor_terms_thread<P, ALL, DAMP>(g, list[i], level, acc);
+        factor_terms_rec<P, DAMP>(g, R.ld_stream(i), acc);
     flush_acc<256>(acc, st);
 }
 
@@ -258,9 +258,8 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
             for (int32_t i = o0 + w; i < o1; i += NW) factor_wave<P, false, DAMP>(g, lst[i], lane, L, acc);
         }
         if (TEAMS) {
-            const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_THREAD];
-            int32_t o0 = plan.fac_lvl_off[FB_TERMS_THREAD][L], o1 = plan.fac_lvl_off[FB_TERMS_THREAD][L + 1];
-            for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_thread<P, false, DAMP>(g, lst[i], L, acc);
+            const int32_t o0 = plan.trec_off[L], o1 = plan.trec_off[L + 1];
+            for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_rec<P, DAMP>(g, plan.trec.ld_stream(i), acc);
         }
         if (TEAMS) {
             const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_WAVE];
@@ -500,6 +499,7 @@ struct Plan {
     int32_t *var_list[VB_COUNT] = {}, *var_lvl_off[VB_COUNT] = {}, *init_var[VB_COUNT] = {};
     int32_t *frec = nullptr, *vrec = nullptr, *frec_off = nullptr, *vrec_off = nullptr;
     int32_t *prec = nullptr, *level_lds = nullptr;
+    int32_t *trec = nullptr, *trec_off = nullptr;
     bool teams() const {
         return !hp.fac_list[FB_WAVE].empty() || !hp.fac_list[FB_BLOCK].empty() ||
                !hp.fac_list[FB_TERMS_WAVE].empty() || !hp.fac_list[FB_TERMS_THREAD].empty();
@@ -524,6 +524,8 @@ struct Plan {
         p.vrec_off = vrec_off;
         p.prec = (const VarRecP *)prec;
         p.level_lds = level_lds;
+        p.trec = (const TermRec *)trec;
+        p.trec_off = trec_off;
         p.stage_slots = hp.stage_slots;
         return p;
     }
@@ -732,6 +734,8 @@ static std::shared_ptr<Plan> make_plan(const Structure &S, const Alloc &alloc, h
     P->vrec_off = P->pool.upload(P->hp.vrec_off, s);
     P->prec = P->pool.upload(P->hp.prec, s);
     P->level_lds = P->pool.upload(P->hp.level_lds, s);
+    P->trec = P->pool.upload(P->hp.trec, s);
+    P->trec_off = P->pool.upload(P->hp.trec_off, s);
     return P;
 }
 
@@ -863,11 +867,9 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         o = pl.fac_lvl_off[FB_TERMS_WAVE][L];
         n = pl.fac_lvl_off[FB_TERMS_WAVE][L + 1] - o;
         if (n) k_fac_terms<PP, ALL, DAMP><<<fac_grid(n, 4), 256, 0, s>>>(dg, P.fac_list[FB_TERMS_WAVE] + o, n, L, g->st);
-        o = pl.fac_lvl_off[FB_TERMS_THREAD][L];
-        n = pl.fac_lvl_off[FB_TERMS_THREAD][L + 1] - o;
-        if (n)
-            k_fac_terms_thread<PP, ALL, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, P.fac_list[FB_TERMS_THREAD] + o, n,
-                                                                               L, g->st);
+        o = pl.trec_off[L];
+        n = pl.trec_off[L + 1] - o;
+        if (n) k_fac_terms_rec<PP, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, (const TermRec *)P.trec + o, n, g->st);
         o = pl.fac_lvl_off[FB_BLOCK][L];
         n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
         if (n)
