@@ -43,8 +43,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "3a450a13a0bc7d3f2ec9532cd8651438966219c5d3da420e726d8bdc2d9a0015",
-                   "bytes_per_launch": 187441500441.7, "raw_bytes_per_launch": 115642240298.0,
+TRAFFIC_DEFAULT = {"sources_sha256": "ff03da862fa1ec06e15c1d79522014eab66a36d64cb85a1510e78b576fd6cfa5",
+                   "bytes_per_launch": 192863751502.7, "raw_bytes_per_launch": 118816065606.6,
                    "queries": 512, "step_iters": 8}
 
 
