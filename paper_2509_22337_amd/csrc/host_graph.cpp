@@ -681,6 +681,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                 }
                 q[2 + n++] = edge_slot[e];
             }
+            if (n == 0) ok = false;  // a staged task reads its belief from its first slot
             q[1] = n | (r[2] & (1 << 30));  // keeps the padding flag
         }
         level_lds[L] = ok ? 1 : 0;

@@ -775,10 +775,12 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
 }
 
 // Loads of one factor of degree D (edges b .. b+D-1, variables u[]), all issued before any is used.
+// On a level staged in LDS, the belief of each written edge's variable (as the factor read it, the
+// value before the level) also goes to the edge's slot in bslots, for the variable phase.
 template <class P, bool DAMP, int D>
 __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
                                                      int type, int32_t fac, unsigned active, const int32_t *u,
-                                                     Acc &acc, typename P::S *slots, int32_t slot0) {
+                                                     Acc &acc, typename P::S *slots, Belief *bslots, int32_t slot0) {
     using S = typename P::S;
     using V = typename P::V;
     S lo[D];
@@ -801,24 +803,29 @@ __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::
     bool nl[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) vf[k] = v2f<P>(B[k], lo[k], nl[k]);
+    if (slots) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if ((active >> k) & 1u) bslots[slot0 + __builtin_popcount(active & ((1u << k) - 1u))] = B[k];
+    }
     factor_local<P, DAMP, D>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
 }
 
 // `slots`: the level's LDS staging area (persistent executor, staged levels), else nullptr.
 template <class P, bool DAMP>
 __device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc,
-                                           typename P::S *slots = nullptr) {
+                                           typename P::S *slots = nullptr, Belief *bslots = nullptr) {
     const int d = r.meta & 0xff, type = (r.meta >> 8) & 0xff;
     const unsigned active = (unsigned)(r.meta >> 16) & 0xffu;
     const int32_t slot0 = r.u[8];
     switch (d) {
-    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
-    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc, slots, slot0); break;
+    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
     default: break;
     }
 }
@@ -867,15 +874,18 @@ __device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
         B.fin -= (double)l;
 }
 
-// Variable task of a staged level: B (its belief before the level, already loaded) plus, for each
-// message the level wrote, new minus old, read from the staging slots. The counts of infinite
-// terms stay exact; the finite part is updated in float64 (the whole belief is rebuilt from the
-// messages at the start of every launch).
+// Variable task of a staged level: its belief before the level (left in bslots by the factor that
+// wrote its first staged message) plus, for each message the level wrote, new minus old, read from
+// the staging slots. The variable phase thus reads LDS only. The counts of infinite terms stay
+// exact; the finite part is updated in float64 (the whole belief is rebuilt from the messages at
+// the start of every launch). A staged task has at least one written message (the host stages a
+// level only then).
 template <class P>
 __device__ __forceinline__ void var_staged(const DevGraph<typename P::S, typename P::V> &g, const VarRecP &r,
-                                           Belief B, const typename P::S *slots) {
+                                           const typename P::S *slots, const Belief *bslots) {
     const int n = r.n & 0xffff;
     const bool pad = (r.n >> 30) & 1;
+    Belief B = bslots[r.s[0]];
 #pragma unroll
     for (int j = 0; j < kStagedEdges; ++j)
         if (j < n) {

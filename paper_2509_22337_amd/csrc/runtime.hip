@@ -215,6 +215,17 @@ struct RunDesc {
     int32_t step;          // > 0: this launch stops the run after `step` more iterations
 };
 
+// Dynamic LDS of a level staged in LDS, for `cap` slots: the (new, old) message pairs (padded to
+// 16 bytes), then one belief per slot.
+template <class S>
+__host__ __device__ constexpr size_t stage_pair_bytes(int32_t cap) {
+    return (sizeof(S) * 2 * size_t(cap) + 15) & ~size_t(15);
+}
+template <class S>
+__host__ __device__ constexpr size_t stage_bytes(int32_t cap) {
+    return stage_pair_bytes<S>(cap) + sizeof(Belief) * size_t(cap);
+}
+
 // Levels [L0, L1) of one run in one workgroup of NT threads, with workgroup barriers between
 // phases. Thread tasks come as records whose loads are issued one phase ahead (the variable records
 // of a level while its factor phase runs, the factor records of the next level while the variable
@@ -226,8 +237,8 @@ struct RunDesc {
 template <class P, bool DAMP, bool TEAMS, int NT, class FOff, class VOff, class Staged>
 __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
                                             int32_t L0, int32_t L1, int32_t Lnext, FOff foff, VOff voff,
-                                            Staged staged, typename P::S *s_slot, TeamLds<typename P::V> *lds,
-                                            Acc &acc, FacRec &fr, VarRecP &pr) {
+                                            Staged staged, typename P::S *s_slot, Belief *b_slot,
+                                            TeamLds<typename P::V> *lds, Acc &acc, FacRec &fr, VarRecP &pr) {
     using S = typename P::S;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -238,20 +249,15 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         const int32_t f0 = foff(L), f1 = foff(L + 1);
         const int32_t v0 = voff(L), v1 = voff(L + 1);
         const bool stg = staged(L);
-        // variable phase inputs, issued now: a staged level needs each variable's belief
-        // before the level; an unstaged one its record
+        // variable phase input of an unstaged level, issued now (a staged level's variable phase
+        // reads LDS only: its records were prefetched, its beliefs come from the factor phase)
         VarRec vr = {};
-        Belief bold = {0.0, 0, 0};
         const VarRecP pc = pr;
-        if (v0 + tid < v1) {
-            if (stg)
-                bold = g.bel.ld(pc.v);
-            else
-                vr = vrec.ld_stream(v0 + tid);
-        }
+        if (v0 + tid < v1 && !stg) vr = vrec.ld_stream(v0 + tid);
         S *const slots = stg ? s_slot : nullptr;
-        if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots);
-        for (int32_t i = f0 + tid + NT; i < f1; i += NT) factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots);
+        if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots, b_slot);
+        for (int32_t i = f0 + tid + NT; i < f1; i += NT)
+            factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots, b_slot);
         if (TEAMS) {
             const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
             int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
@@ -294,11 +300,8 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
             }
         }
         if (stg) {
-            if (v0 + tid < v1) var_staged<P>(g, pc, bold, s_slot);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) {
-                const VarRecP q = prec.ld_stream(i);
-                var_staged<P>(g, q, g.bel.ld(q.v), s_slot);
-            }
+            if (v0 + tid < v1) var_staged<P>(g, pc, s_slot, b_slot);
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_staged<P>(g, prec.ld_stream(i), s_slot, b_slot);
         } else {
             if (v0 + tid < v1) var_rec<P>(g, vr);
             for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
@@ -323,11 +326,13 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     __shared__ double red_r[NW];
     __shared__ unsigned int red_c[NW];
     __shared__ int s_done;
-    // dynamic LDS: staging slots (new, old message pairs of a staged level's written edges), then
-    // the per-level factor record offsets, variable record offsets and staging flags
+    // dynamic LDS: staging slots (new, old message pairs of a staged level's written edges), the
+    // beliefs before the level of those edges' variables, then the per-level factor record
+    // offsets, variable record offsets and staging flags
     extern __shared__ __align__(16) unsigned char s_dyn[];
     S *const s_slot = (S *)s_dyn;
-    int32_t *const s_off = (int32_t *)(s_dyn + sizeof(S) * 2 * size_t(stage_cap));
+    Belief *const b_slot = (Belief *)(s_dyn + stage_pair_bytes<S>(stage_cap));
+    int32_t *const s_off = (int32_t *)(s_dyn + stage_bytes<S>(stage_cap));
     const RunDesc<P> &D = descs[blockIdx.x];
     const DevGraph<typename P::S, typename P::V> g = D.g;
     const DevPlan plan = D.plan;
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     if (NL > 0 && staged(0) && voff(0) + tid < voff(1)) pr = prec.ld_stream(voff(0) + tid);
     while (!s_done) {
         Acc acc = {0.0, 0u};
-        level_range<P, DAMP, TEAMS, NT>(g, plan, 0, NL, 0, foff, voff, staged, s_slot, &lds, acc, fr, pr);
+        level_range<P, DAMP, TEAMS, NT>(g, plan, 0, NL, 0, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
         // end of iteration: block-wide residual and contradiction count
         double r = acc.r;
         unsigned int c = acc.contra;
@@ -419,6 +424,7 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
     extern __shared__ __align__(16) unsigned char s_dyn[];
     if (st->done) return;
     S *const s_slot = (S *)s_dyn;
+    Belief *const b_slot = (Belief *)(s_dyn + stage_pair_bytes<S>(stage_cap));
     const int tid = threadIdx.x;
     const bool staging = plan.stage_slots > 0 && plan.stage_slots <= stage_cap;
     auto foff = [&](int32_t L) { return (int32_t)plan.frec_off[L]; };
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
     if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld_stream(foff(L0) + tid);
     if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr = plan.prec.ld_stream(voff(L0) + tid);
     Acc acc = {0.0, 0u};
-    level_range<P, DAMP, TEAMS, NT>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, &lds, acc, fr, pr);
+    level_range<P, DAMP, TEAMS, NT>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
     flush_acc<NT>(acc, st);
 }
 
@@ -829,7 +835,7 @@ template <class PP, bool DAMP>
 static void launch_fused(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, const DevPlan &dp,
                          int32_t L0, int32_t L1, bool teams, hipStream_t s) {
     const int32_t cap = g->P->hp.stage_slots;
-    const size_t lds = sizeof(typename PP::S) * 2 * size_t(std::max(cap, 1));
+    const size_t lds = stage_bytes<typename PP::S>(std::max(cap, 1));
     const int nt = persistent_threads(g->precision(), teams, 1);
     if constexpr (std::is_same<PP, PolLog32>::value) {
         if (nt == 1024) {
@@ -995,7 +1001,7 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
         max_levels = std::max(max_levels, gs[i]->P->hp.exec_levels);
         stage_cap = std::max(stage_cap, gs[i]->P->hp.stage_slots);
     }
-    const size_t slot_bytes = sizeof(typename PP::S) * 2 * size_t(stage_cap);
+    const size_t slot_bytes = stage_bytes<typename PP::S>(stage_cap);
     int32_t lds_levels = std::min<int32_t>(max_levels, 4095);
     if (slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1) > (size_t(64) << 10)) lds_levels = 0;
     const size_t lds_bytes = slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1);
