@@ -717,7 +717,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         }
         int32_t e = L;
         bool teams = false;
-        while (e < exec_levels && narrow[e]) {
+        while (e < exec_levels && narrow[e] && e - L < kFuseMaxLevels) {
             teams = teams || cnt(fac_lvl_off[FB_WAVE], e) + cnt(fac_lvl_off[FB_TERMS_WAVE], e) +
                                      cnt(fac_lvl_off[FB_TERMS_THREAD], e) + cnt(var_lvl_off[VB_WAVE], e) > 0;
             ++e;

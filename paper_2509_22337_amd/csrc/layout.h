@@ -111,6 +111,7 @@ constexpr int kVarRecEdges = 5;      // edge ids held in a variable task record 
 // records and variable records, no workgroup-per-factor task and few wavefront tasks.
 constexpr int kFuseMaxRecs = 2048;
 constexpr int kFuseMaxWaveTasks = 128;
+constexpr int kFuseMaxLevels = 2048;  // levels of one fused launch (their offsets go to LDS)
 
 // Factors given as weighted terms: FB_TERMS_THREAD one thread per factor (degree <= kThreadMaxDeg),
 // FB_TERMS_WAVE one wavefront per factor (degree up to 64)

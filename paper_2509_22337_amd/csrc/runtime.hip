@@ -234,7 +234,7 @@ __host__ __device__ constexpr size_t stage_bytes(int32_t cap) {
 // exit they hold those of level `Lnext` (none when Lnext < 0). TEAMS adds the wavefront- and
 // workgroup-per-factor paths and the weighted-term paths. foff / voff / staged give each level's
 // record offsets and staging flag.
-template <class P, bool DAMP, bool TEAMS, int NT, class FOff, class VOff, class Staged>
+template <class P, bool DAMP, bool TEAMS, int NT, bool UNCOND, class FOff, class VOff, class Staged>
 __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
                                             int32_t L0, int32_t L1, int32_t Lnext, FOff foff, VOff voff,
                                             Staged staged, typename P::S *s_slot, Belief *b_slot,
@@ -289,14 +289,26 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         }
         {
             // records of the next level (Lnext after the last level of the range)
+            // UNCOND: unconditional loads, record 0 for threads without one (never used: the phases
+            // check the index again), since a conditional load makes the compiler wait for it at
+            // once; the conditional form needs fewer registers
             const int32_t Ln = (L + 1 < L1) ? L + 1 : Lnext;
-            fr = FacRec{};
-            pr = VarRecP{};
-            if (Ln >= 0) {
-                const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
-                if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
-                const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
+            if (UNCOND) {
+                if (Ln >= 0) {
+                    const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
+                    fr = frec.ld_stream(n0 + tid < n1 ? n0 + tid : 0);
+                    const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
+                    pr = prec.ld_stream(staged(Ln) && m0 + tid < m1 ? m0 + tid : 0);
+                }
+            } else {
+                fr = FacRec{};
+                pr = VarRecP{};
+                if (Ln >= 0) {
+                    const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
+                    if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
+                    const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
+                    if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
+                }
             }
         }
         if (stg) {
@@ -316,8 +328,10 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
 
 // One workgroup of NT threads runs every level and iteration of one run. Used when the levels are
 // too narrow to fill the GPU. A launch returns when the run is done or its iteration count reaches
-// st->step_end, so a caller can advance many runs in steps.
-template <class P, bool DAMP, bool TEAMS, int NT>
+// st->step_end, so a caller can advance many runs in steps. OFFL: every run's per-level offsets and
+// flags fit the launch's LDS table (else they are read from memory); a compile-time choice, so the
+// level loop has one path and the compiler's memory waits stay precise.
+template <class P, bool DAMP, bool TEAMS, int NT, bool OFFL>
 __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int32_t lds_levels, int32_t stage_cap) {
     using S = typename P::S;
     using V = typename P::V;
@@ -345,17 +359,16 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     const bool staging = plan.stage_slots > 0 && plan.stage_slots <= stage_cap;
     // per-level offsets and flags: staged once in LDS so that a level does not start with a round
     // trip to memory (schedules deeper than the launch's LDS allowance read them from memory)
-    const bool off_lds = NL <= lds_levels;
-    if (off_lds)
+    if (OFFL)
         for (int32_t i = tid; i <= NL; i += NT) {
             s_off[i] = plan.frec_off[i];
             s_off[lds_levels + 1 + i] = plan.vrec_off[i];
             s_off[2 * (lds_levels + 1) + i] = (staging && i < NL) ? (int32_t)plan.level_lds[i] : 0;
         }
-    auto foff = [&](int32_t L) { return off_lds ? s_off[L] : (int32_t)plan.frec_off[L]; };
-    auto voff = [&](int32_t L) { return off_lds ? s_off[lds_levels + 1 + L] : (int32_t)plan.vrec_off[L]; };
+    auto foff = [&](int32_t L) { return OFFL ? s_off[L] : (int32_t)plan.frec_off[L]; };
+    auto voff = [&](int32_t L) { return OFFL ? s_off[lds_levels + 1 + L] : (int32_t)plan.vrec_off[L]; };
     auto staged = [&](int32_t L) {
-        return off_lds ? s_off[2 * (lds_levels + 1) + L] != 0 : (staging && plan.level_lds[L] != 0);
+        return OFFL ? s_off[2 * (lds_levels + 1) + L] != 0 : (staging && plan.level_lds[L] != 0);
     };
     for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
     for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
@@ -367,11 +380,13 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     // records of level 0: the factor record, and the staged variable record when level 0 is staged
     FacRec fr = {};
     VarRecP pr = {};
-    if (NL > 0 && foff(0) + tid < foff(1)) fr = frec.ld_stream(foff(0) + tid);
-    if (NL > 0 && staged(0) && voff(0) + tid < voff(1)) pr = prec.ld_stream(voff(0) + tid);
+    if (NL > 0) {
+        fr = frec.ld_stream(foff(0) + tid < foff(1) ? foff(0) + tid : 0);
+        pr = prec.ld_stream(staged(0) && voff(0) + tid < voff(1) ? voff(0) + tid : 0);
+    }
     while (!s_done) {
         Acc acc = {0.0, 0u};
-        level_range<P, DAMP, TEAMS, NT>(g, plan, 0, NL, 0, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
+        level_range<P, DAMP, TEAMS, NT, true>(g, plan, 0, NL, 0, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
         // end of iteration: block-wide residual and contradiction count
         double r = acc.r;
         unsigned int c = acc.contra;
@@ -435,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
     if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld_stream(foff(L0) + tid);
     if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr = plan.prec.ld_stream(voff(L0) + tid);
     Acc acc = {0.0, 0u};
-    level_range<P, DAMP, TEAMS, NT>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
+    level_range<P, DAMP, TEAMS, NT, false>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
     flush_acc<NT>(acc, st);
 }
 
@@ -1006,8 +1021,14 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     if (slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1) > (size_t(64) << 10)) lds_levels = 0;
     const size_t lds_bytes = slot_bytes + sizeof(int32_t) * 3 * size_t(lds_levels + 1);
     HIPCHK(hipEventRecord(lc.k0, s));
-#define FASTLBP_LAUNCH(DA, TE, NT_) \
-    k_persistent<PP, DA, TE, NT_><<<n, NT_, lds_bytes, s>>>(dd, lds_levels, stage_cap)
+    const bool offl = max_levels <= lds_levels;
+#define FASTLBP_LAUNCH(DA, TE, NT_)                                                        \
+    do {                                                                                   \
+        if (offl)                                                                          \
+            k_persistent<PP, DA, TE, NT_, true><<<n, NT_, lds_bytes, s>>>(dd, lds_levels, stage_cap);  \
+        else                                                                               \
+            k_persistent<PP, DA, TE, NT_, false><<<n, NT_, lds_bytes, s>>>(dd, lds_levels, stage_cap); \
+    } while (0)
     bool launched = false;
     if constexpr (std::is_same<PP, PolLog32>::value) {
         if (nt == 1024) {
