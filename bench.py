@@ -43,8 +43,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "ff03da862fa1ec06e15c1d79522014eab66a36d64cb85a1510e78b576fd6cfa5",
-                   "bytes_per_launch": 192863751502.7, "raw_bytes_per_launch": 118816065606.6,
+TRAFFIC_DEFAULT = {"sources_sha256": "31b4714cb3264526fd0ef41714495d8f5ea68d711170594680c817201346c7b0",
+                   "bytes_per_launch": 206388724709.6, "raw_bytes_per_launch": 126011867136.0,
                    "queries": 512, "step_iters": 8}
 
 
