@@ -125,3 +125,49 @@ def test_server_errors():
     assert ei.value.code == F.E_TOO_LARGE
     srv.close()
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_server_steps_hybrid_runs(precision):
+    # an alarm graph under the round-robin order (one wide level, ~180 narrow ones: AUTO picks the
+    # HYBRID executor) served beside narrow graphs, with warm re-queries that clamp alarms: equal
+    # to the same requests run alone, and to the oracle
+    wa = W.alarm_graph(0, num_inputs=1500, num_derived=3000, num_alarms=40)
+    wa.edge_rank = W.seqfix_ranks(wa)
+    wa.max_iters, wa.tol, wa.damping = 20, 0.0, 0.0
+    ws = [wa, W.smartfl(4, levels=30, width=60, max_iters=100)]
+    reqs = [(0, np.zeros(0, np.int32), np.zeros(0, np.int8)), (1, np.zeros(0, np.int32), np.zeros(0, np.int8))]
+    for k in range(3):
+        reqs.append((0, wa.alarms[k:k + 1].astype(np.int32), wa.labels[k:k + 1].astype(np.int8)))
+    params = [(w.max_iters, w.tol, w.damping) for w in ws]
+    solo = [F.Graph.from_workload(w, precision=precision) for w in ws]
+    alone = []
+    for gi, v, x in reqs:
+        solo[gi].evidence_set(v, x)
+        st = solo[gi].run(*params[gi])
+        alone.append((solo[gi].marginals(), st))
+    srv = F.Server(precision=precision, max_active=2, step_iters=4)
+    hs = [F.Graph.from_workload(w, precision=precision) for w in ws]
+    tickets = [srv.submit(hs[gi], v, x, *params[gi]) for gi, v, x in reqs]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    ev_cur = [np.array(w.evidence, dtype=np.int8, copy=True) for w in ws]
+    state = [None, None]
+    for i, (gi, v, x) in enumerate(reqs):
+        w = ws[gi]
+        ev_cur[gi][v] = x
+        m_srv, st_srv, _ = results[i]
+        m_alone, st_alone = alone[i]
+        E = w.num_edges
+        m0, m1 = state[gi] if state[gi] is not None else (np.full(E, 0.5), np.full(E, 0.5))
+        om, om0, om1, _ = oracle.bp_pairs(w, m0, m1, w.max_iters, w.tol, w.damping, ranks=w.edge_rank,
+                                          evidence=ev_cur[gi])
+        state[gi] = (om0, om1)
+        _say("hybrid serving", precision, i, w.name, st_srv["executor"], np.abs(m_srv - m_alone).max(),
+             np.abs(m_srv - om).max())
+        assert st_srv["executor"] == st_alone["executor"] == (F.EXEC_HYBRID if gi == 0 else F.EXEC_PERSISTENT)
+        assert st_srv["iterations"] == st_alone["iterations"]
+        assert np.abs(m_srv - m_alone).max() <= (1e-12 if precision == "fp64" else 1e-6)
+        assert np.abs(m_srv - om).max() <= TOL[precision]
+    for h in hs + solo:
+        h.close()
