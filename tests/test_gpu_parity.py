@@ -398,3 +398,18 @@ def test_messages_roundtrip_and_reset():
     with pytest.raises(F.FastLBPError):
         g.run(5, 0.0, 1.0)
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_schedule_deeper_than_the_lds_offset_table(precision):
+    # 4,699 executed levels: more than the persistent kernel's LDS table of per-level offsets
+    # (4,095), so the launch takes the build that reads them from memory
+    w = W.smartfl(2, levels=2400, width=6, max_iters=6)
+    om, omsg, _ = oracle.bp(w, 6, 0.0, 0.0)
+    for executor in ("persistent", "levels"):
+        _say("deep schedule", precision, executor)
+        m, msgs, st, lv = _gpu_run(w, precision, executor, max_iters=6, tol=0.0, damping=0.0)
+        assert int(lv.max()) + 1 > 4096
+        assert st["executor"] == (F.EXEC_PERSISTENT if executor == "persistent" else F.EXEC_LEVELS)
+        assert np.abs(m - om).max() <= TOL[precision], executor
+        assert np.abs(msgs - omsg).max() <= TOL[precision], executor
