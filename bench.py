@@ -48,6 +48,12 @@ TRAFFIC_DEFAULT = {"sources_sha256": "31b4714cb3264526fd0ef41714495d8f5ea68d7111
                    "queries": 512, "step_iters": 8}
 
 
+# The same for the serving configuration (512 graphs, 512 active runs, 8 iterations per launch):
+# average k_persistent launch of the server. Empty until profiled.
+TRAFFIC_SERVING = {"sources_sha256": "", "bytes_per_launch": None, "queries": 512, "max_active": 512,
+                   "step_iters": 8}
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     import glob
@@ -94,7 +100,7 @@ def batched_steps(F, w, queries, steps, warmup, step_iters):
                 lat.append(l)
                 updates += st["message_updates"]
                 iters.append(st["iterations"])
-                alg_bytes += st["algorithmic_bytes_per_iter"] * st["iterations"]
+                alg_bytes += st["method_bytes_per_iter"] * st["iterations"]
         log(f"batched step {s}: {max(r[2] for r in res):.1f} ms, iterations {sorted(r[1]['iterations'] for r in res)[::8]}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -131,33 +137,22 @@ def sequential_queries(F, w, queries, precision):
     return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, device_ms=dev_ms)
 
 
-def serving_mix(F, W, args):
-    """The serving mix: graphs of log-uniform size (half Datalog-, half SmartFL-shaped) arriving as
-    a Poisson process; when a query completes, it is re-submitted warm with 1-10 new clamps. The
-    batched FP32 server takes the arrivals as they come; the plain FP64 side runs a prefix of the same
-    query list one run at a time (cold then warm re-query), without arrivals."""
+def _replay_fp32(F, W, qs, hs, args, clamps):
+    """The batched FP32 server on a stream: each graph's first query is submitted at its arrival
+    time; when it completes, its warm re-query (1-10 new clamps, recorded in `clamps` for the plain
+    FP64 side) is submitted at once. Returns per-run results and the server's statistics."""
     import torch
-    qs = W.serving_mix(args.seed, num_queries=args.queries)
-    log(f"serving mix: {len(qs)} graphs, {sum(q.graph.num_vars for q in qs)} variables, "
-        f"{sum(q.graph.num_edges for q in qs)} edges, last arrival {qs[-1].arrival_s:.2f} s")
-    t0 = time.perf_counter()
-    hs = [F.Graph.from_workload(q.graph, precision="fp32") for q in qs]
-    log(f"created {len(hs)} fp32 handles in {time.perf_counter() - t0:.1f} s")
-    for h in hs:
-        h.evidence_clear()
     srv = F.Server(precision="fp32", max_active=args.batch, step_iters=args.step_iters)
     torch.cuda.synchronize()
     st0 = srv.stats()
-    pending = {}
-    res = []
-    nq = len(qs)
-    nxt = 0
+    pending, res, nxt, nq = {}, [], 0, len(qs)
     t_start = time.perf_counter()
     while len(res) < 2 * nq:
         now = time.perf_counter() - t_start
         while nxt < nq and qs[nxt].arrival_s <= now:
             q = qs[nxt]
-            pending[srv.submit(hs[nxt], q.ev_vars, q.ev_vals, q.graph.max_iters, q.graph.tol, q.graph.damping)] = (nxt, 0)
+            t = srv.submit(hs[nxt], q.ev_vars, q.ev_vals, q.graph.max_iters, q.graph.tol, q.graph.damping)
+            pending[t] = (nxt, 0)
             nxt += 1
         for t in list(pending):
             r = srv.poll(t)
@@ -165,87 +160,176 @@ def serving_mix(F, W, args):
                 continue
             qi, warm = pending.pop(t)
             p1, st, lat = r
-            res.append((qi, warm, st, lat))
+            res.append(dict(q=qi, warm=warm, stats=st, lat_ms=lat, p1=p1 if qi < args.fp64_graphs else None))
             if not warm:
                 q = qs[qi]
                 v, x = W.requery_clamps(q.graph, p1, seed=10_000 + qi)
-                pending[srv.submit(hs[qi], v, x, q.graph.max_iters, q.graph.tol, q.graph.damping)] = (qi, 1)
+                clamps[qi] = (v, x)
+                t2 = srv.submit(hs[qi], v, x, q.graph.max_iters, q.graph.tol, q.graph.damping)
+                pending[t2] = (qi, 1)
         time.sleep(0.0002)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     st1 = srv.stats()
     srv.close()
+    d = {k: st1[k] - st0[k] for k in ("kernel_ms", "steps", "persistent_launches", "persistent_ms",
+                                       "persistent_method_bytes", "method_bytes")}
+    d.update(evictions=st1["evictions"], restores=st1["restores"], peak_resident_bytes=st1["peak_resident_bytes"])
+    return res, wall, d
+
+
+def _fifo_fp64(F, qs, clamps, n_graphs):
+    """Plain FP64 single-graph BP as a FIFO server on the same stream: one run at a time on the GPU
+    (fastlbp_run, the executor the library picks for the graph), in arrival order; a graph's warm
+    re-query arrives when its first run completes and joins the queue's tail. Latency = completion
+    - arrival, queueing included."""
+    import torch
+    hs = [F.Graph.from_workload(q.graph, precision="fp64") for q in qs[:n_graphs]]
+    for h in hs:
+        h.evidence_clear()
+    torch.cuda.synchronize()
+    queue = [(qs[i].arrival_s, i, 0) for i in range(n_graphs)]
+    res, upd, busy = [], 0, 0.0
+    t_start = time.perf_counter()
+    while queue:
+        queue.sort()
+        arr, qi, warm = queue.pop(0)
+        now = time.perf_counter() - t_start
+        if arr > now:
+            time.sleep(arr - now)
+        q = qs[qi]
+        v, x = clamps[qi] if warm else (q.ev_vars, q.ev_vals)
+        t0 = time.perf_counter()
+        hs[qi].evidence_set(v, x)
+        st = hs[qi].run(q.graph.max_iters, q.graph.tol, q.graph.damping)
+        p1 = hs[qi].marginals()
+        t1 = time.perf_counter()
+        busy += t1 - t0
+        upd += st["message_updates"]
+        done = t1 - t_start
+        res.append(dict(q=qi, warm=warm, stats=st, lat_ms=(done - arr) * 1e3, service_ms=(t1 - t0) * 1e3, p1=p1))
+        if not warm:
+            queue.append((done, qi, 1))
+    wall = time.perf_counter() - t_start
     for h in hs:
         h.close()
-    upd = sum(r[2]["message_updates"] for r in res)
-    alg = sum(r[2]["algorithmic_bytes_per_iter"] * r[2]["iterations"] for r in res)
-    cold = [r[3] for r in res if r[1] == 0]
-    warm = [r[3] for r in res if r[1] == 1]
-    out = dict(mups=round(upd / wall, 1), wall_s=round(wall, 3), runs=len(res), queries_per_s=round(len(res) / wall, 2),
-               p50_ms=pct([r[3] for r in res], 50), p99_ms=pct([r[3] for r in res], 99),
-               cold_p50_ms=pct(cold, 50), cold_p99_ms=pct(cold, 99), warm_p50_ms=pct(warm, 50),
-               warm_p99_ms=pct(warm, 99),
-               iterations_p50=int(np.median([r[2]["iterations"] for r in res])),
-               levels_executor_runs=int(sum(r[2]["executor"] == F.EXEC_LEVELS for r in res)),
-               kernel_ms=st1["kernel_ms"] - st0["kernel_ms"], steps=st1["steps"] - st0["steps"],
-               algorithmic_bytes=alg, updates=upd)
-    log(f"serving fp32: {out['runs']} runs in {wall:.2f} s, {upd / wall / 1e6:.1f} M updates/s, "
-        f"p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms")
-    # plain FP64: the first fp64_queries graphs, each a cold run then its warm re-query, one at a time
-    lat64, upd64, t64 = [], 0, 0.0
-    for qi in range(min(args.fp64_queries, nq)):
-        q = qs[qi]
-        g = F.Graph.from_workload(q.graph, precision="fp64")
-        g.evidence_clear()
-        for warm in (0, 1):
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            if warm:
-                v, x = W.requery_clamps(q.graph, p1, seed=10_000 + qi)
-            else:
-                v, x = q.ev_vars, q.ev_vals
-            g.evidence_set(v, x)
-            st = g.run(q.graph.max_iters, q.graph.tol, q.graph.damping)
-            p1 = g.marginals()
-            dt = time.perf_counter() - ta
-            lat64.append(dt * 1e3)
-            upd64 += st["message_updates"]
-            t64 += dt
-        g.close()
-    out["plain_fp64"] = dict(mups=round(upd64 / t64, 1), runs=len(lat64), p50_ms=pct(lat64, 50),
-                             p99_ms=pct(lat64, 99), note="service time of each run alone, no queueing")
-    return out
+    return res, wall, upd, busy
 
 
-def flooding_runs(F, w, prec, steps, warmup, iters, label):
-    """`steps` timed cold runs of `iters` flooding iterations on the LEVELS executor."""
+def _lat(rs, warm=None):
+    a = [r["lat_ms"] for r in rs if warm is None or r["warm"] == warm]
+    return dict(p50_ms=pct(a, 50), p99_ms=pct(a, 99)) if a else {}
+
+
+def serving_mix(F, W, args):
+    """The serving configuration: 512 graphs with sizes log-uniform in [1k, 500k] variables, half
+    Datalog-shaped (flooding, damping 0.5), half SmartFL-shaped (forward-backward ranks, 2%
+    clamps), arriving as a Poisson process at 200 queries/s; when a query completes it is
+    re-submitted warm with 1-10 new clamps (1,024 runs); tol 1e-6, at most 100 iterations each.
+
+    * batched FP32 (the value): the continuous-batching server on the whole stream.
+    * plain FP64: a FIFO server running one FP64 graph at a time with fastlbp_run, on the same
+      arrival stream and the same re-query clamps, over the stream's first --fp64-graphs graphs (a
+      bounded prefix: the FIFO queue falls behind the arrivals, so running all of it would take
+      minutes); the batched FP32 server's latencies on the same prefix are reported beside it.
+    * the FP32 error: FP32 marginals against the FP64 ones of the same runs on the prefix (the FP64
+      path matches the oracle to 1e-9 in the tests)."""
+    qs = W.serving_mix(args.seed, num_queries=args.queries)
+    log(f"serving mix: {len(qs)} graphs, {sum(q.graph.num_vars for q in qs)} variables, "
+        f"{sum(q.graph.num_edges for q in qs)} edges, last arrival {qs[-1].arrival_s:.2f} s")
+    t0 = time.perf_counter()
+    hs = [F.Graph.from_workload(q.graph, precision="fp32") for q in qs]
+    for h in hs:
+        h.evidence_clear()
+    log(f"created {len(hs)} fp32 handles in {time.perf_counter() - t0:.1f} s")
+    clamps = {}
+    res, wall, sd = _replay_fp32(F, W, qs, hs, args, clamps)
+    for h in hs:
+        h.close()
+    upd = sum(r["stats"]["message_updates"] for r in res)
+    log(f"batched fp32: {len(res)} runs in {wall:.2f} s, {upd / wall / 1e9:.3f} G updates/s, "
+        f"p50 {_lat(res)['p50_ms']} ms p99 {_lat(res)['p99_ms']} ms")
+    n64 = min(args.fp64_graphs, len(qs))
+    r64, wall64, upd64, busy64 = _fifo_fp64(F, qs, clamps, n64)
+    log(f"plain fp64 FIFO on the first {n64} graphs: {len(r64)} runs in {wall64:.2f} s, "
+        f"{upd64 / busy64 / 1e6:.1f} M updates/s busy, p50 {_lat(r64)['p50_ms']} ms p99 {_lat(r64)['p99_ms']} ms")
+    pre = [r for r in res if r["q"] < n64]
+    upd_pre = sum(r["stats"]["message_updates"] for r in pre)
+    # FP32 error against FP64 on the same runs (same graph, clamps and warm start)
+    e64 = {(r["q"], r["warm"]): r for r in r64}
+    errs, errs_conv = [], []
+    for r in pre:
+        o = e64[(r["q"], r["warm"])]
+        e = float(np.abs(r["p1"] - o["p1"]).max())
+        errs.append(e)
+        if r["stats"]["converged"] and o["stats"]["converged"]:
+            errs_conv.append(e)
+    out = dict(
+        runs=len(res), wall_s=round(wall, 3), mups=round(upd / wall, 1), queries_per_s=round(len(res) / wall, 2),
+        latency=dict(all=_lat(res), cold=_lat(res, 0), warm=_lat(res, 1)),
+        iterations_p50=int(np.median([r["stats"]["iterations"] for r in res])),
+        converged=int(sum(r["stats"]["converged"] for r in res)),
+        executors={n: int(sum(r["stats"]["executor"] == e for r in res))
+                   for n, e in (("persistent", F.EXEC_PERSISTENT), ("levels", F.EXEC_LEVELS), ("hybrid", F.EXEC_HYBRID))},
+        server=sd, updates=upd,
+        prefix=dict(graphs=n64, runs=len(pre), latency=dict(all=_lat(pre), cold=_lat(pre, 0), warm=_lat(pre, 1))),
+        plain_fp64=dict(graphs=n64, runs=len(r64), wall_s=round(wall64, 3), busy_s=round(busy64, 3),
+                        mups_busy=round(upd64 / busy64, 1),
+                        latency=dict(all=_lat(r64), cold=_lat(r64, 0), warm=_lat(r64, 1)),
+                        service_p50_ms=pct([r["service_ms"] for r in r64], 50),
+                        note="FIFO single-graph FP64 server (fastlbp_run one graph at a time) on the stream's "
+                             "first graphs, same arrival times and re-query clamps; latency includes queueing"),
+        fp32_error=dict(vs="FP64 marginals of the same runs (plain FP64 leg)", runs=len(errs),
+                        max_abs=max(errs) if errs else None, runs_both_converged=len(errs_conv),
+                        max_abs_both_converged=max(errs_conv) if errs_conv else None),
+        prefix_updates=upd_pre)
+    return qs, res, out
+
+
+def flooding_runs(F, w, prec, steps, warmup, iters, label, tol=0.0):
+    """`steps` timed cold runs of at most `iters` iterations on the LEVELS executor; the marginals of
+    the last run are returned for the FP32-vs-FP64 comparison."""
     import torch
     g = F.Graph.from_workload(w, precision=prec, executor="levels")
     for s in range(warmup + steps):
         if s == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            dev_ms, upd, alg = 0.0, 0, 0.0
+            dev_ms, upd, mb, ib, its = 0.0, 0, 0.0, 0.0, 0
         g.messages_reset()
-        st = g.run(iters, 0.0, 0.0)
+        st = g.run(iters, tol, 0.0)
         if s >= warmup:
             dev_ms += st["device_ms"]
             upd += st["message_updates"]
-            alg += st["algorithmic_bytes_per_iter"] * st["iterations"]
+            mb += st["method_bytes_per_iter"] * st["iterations"]
+            ib += st["impl_bytes_per_iter"] * st["iterations"]
+            its += st["iterations"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    m = g.marginals()
     g.close()
-    r = dict(wall_s=wall, dev_ms=dev_ms, updates=upd, alg=alg, iters=st["iterations"], steps=steps,
-             mups=round(upd / wall, 1), us_per_iteration=round(dev_ms * 1e3 / (steps * st["iterations"]), 2))
+    r = dict(wall_s=wall, dev_ms=dev_ms, updates=upd, method_bytes=mb, impl_bytes=ib, iters=st["iterations"],
+             steps=steps, converged=st["converged"], residual=st["residual"], levels=st["levels"],
+             mups=round(upd / wall, 1), us_per_iteration=round(dev_ms * 1e3 / max(1, its), 2), marginals=m)
     log(f"{label} {prec}: {wall * 1e3 / steps:.1f} ms/run, {upd / wall / 1e9:.2f} G updates/s, "
-        f"{r['us_per_iteration']:.1f} us/iteration")
+        f"{r['us_per_iteration']:.1f} us/iteration, {st['iterations']} iterations")
     return r
+
+
+def _roofline_levels(r, kernel):
+    achieved = r["method_bytes"] / (r["dev_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernel,
+            "impl_bytes_achieved_gbs": round(r["impl_bytes"] / (r["dev_ms"] / 1e3) / 1e9, 2),
+            "bytes_note": "method bytes per iteration (4 + 5s per edge under flooding, s = 4, + s per NOISY_OR "
+                          "activation; ranked: exact from the levels) over the runs' device time (HIP events)"}
 
 
 def bingo_flooding(F, W, args, terms=False):
     """One BINGO-shaped graph (2M tuples, 4M rules, 19M edges), flooding, FP32 messages, on the
     LEVELS executor: per iteration one launch per degree bucket and phase. A step is one run of
-    --max-iters (default 100) iterations; FP64 runs the same graph for the plain comparison.
+    --max-iters (default 100) iterations; FP64 runs the same graph for the plain comparison and the
+    FP32 error (FP32 marginals against FP64 after the same iterations from uniform messages).
     terms: the 4M rule factors given as weighted terms (Eq.(4)) instead of AND factors; the typed
     graph's FP32 time is reported beside it."""
     w = W.config("C3", seed=args.seed)
@@ -259,7 +343,6 @@ def bingo_flooding(F, W, args, terms=False):
     res = {prec: flooding_runs(F, w, prec, args.steps if prec == "fp32" else 1, args.warmup, iters, "bingo")
            for prec in ("fp32", "fp64")}
     r = res["fp32"]
-    achieved = r["alg"] / (r["dev_ms"] / 1e3) / 1e9
     name = "bingo_2M_tuples_4M_rules_19M_edges_flooding" + ("_rules_as_weighted_terms" if terms else "")
     out = {
         "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
@@ -270,9 +353,9 @@ def bingo_flooding(F, W, args, terms=False):
                    "iterations": iters, "executor": "levels"},
         "us_per_iteration": r["us_per_iteration"],
         "plain_fp64": {"mups": res["fp64"]["mups"], "us_per_iteration": res["fp64"]["us_per_iteration"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "one iteration of the LEVELS executor (all kernels)"},
+        "fp32_error": {"vs": f"FP64 marginals after the same {iters} iterations from uniform messages",
+                       "max_abs": float(np.abs(r["marginals"] - res["fp64"]["marginals"]).max())},
+        "roofline": _roofline_levels(r, "one iteration of the LEVELS executor (all kernels)"),
     }
     if typed:
         out["typed_fp32"] = {"mups": typed["mups"], "us_per_iteration": typed["us_per_iteration"]}
@@ -283,47 +366,29 @@ def bingo_flooding(F, W, args, terms=False):
 def bingo_large(F, W, args):
     """One BINGO-shaped graph ten times the size of the flooding one (20M tuples, 40M rules, 190M
     edges) under an ordered-group schedule of 64 classes by head position, FP32 messages, tol 1e-6,
-    up to 200 iterations (--max-iters overrides), on the LEVELS executor. A step is one cold run."""
-    import torch
+    up to 200 iterations (--max-iters overrides), on the LEVELS executor. A step is one cold run.
+    One FP64 run of the same graph gives the plain comparison and the FP32 error at convergence."""
     t0 = time.perf_counter()
     w = W.config("C5", seed=args.seed)
     iters = args.max_iters or w.max_iters
     log(f"workload bingo-large: V={w.num_vars} F={w.num_factors} E={w.num_edges}, generated in "
         f"{time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    g = F.Graph.from_workload(w, precision="fp32", executor="levels")
-    log(f"created in {time.perf_counter() - t0:.1f} s")
-    del w
-    dev_ms, upd, alg, its = 0.0, 0, 0.0, []
-    for s in range(args.warmup + args.steps):
-        if s == args.warmup:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        g.messages_reset()
-        st = g.run(iters, 1e-6, 0.0)
-        log(f"run {s}: {st['iterations']} iterations, converged {st['converged']}, residual {st['residual']:.3g}, "
-            f"{st['device_ms']:.1f} ms")
-        if s >= args.warmup:
-            dev_ms += st["device_ms"]
-            upd += st["message_updates"]
-            alg += st["algorithmic_bytes_per_iter"] * st["iterations"]
-            its.append(st["iterations"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    levels = st["levels"]
-    g.close()
-    achieved = alg / (dev_ms / 1e3) / 1e9
+    res = {prec: flooding_runs(F, w, prec, args.steps if prec == "fp32" else 1, args.warmup if prec == "fp32" else 0,
+                               iters, "bingo-large", tol=1e-6) for prec in ("fp32", "fp64")}
+    r = res["fp32"]
     return {
         "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
-        "value": round(upd / wall, 1), "unit": "message updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
+        "value": round(r["updates"] / r["wall_s"], 1), "unit": "message updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["wall_s"] * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "bingo_20M_tuples_40M_rules_190M_edges_64_ordered_groups", "seed": args.seed,
-                   "levels": levels, "max_iters": iters, "tol": 1e-6, "executor": "levels"},
-        "iterations": its, "us_per_iteration": round(dev_ms * 1e3 / sum(its), 2),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "one iteration of the LEVELS executor (all kernels)"},
+                   "levels": r["levels"], "max_iters": iters, "tol": 1e-6, "executor": "levels"},
+        "iterations": r["iters"], "converged": r["converged"], "us_per_iteration": r["us_per_iteration"],
+        "plain_fp64": {"mups": res["fp64"]["mups"], "us_per_iteration": res["fp64"]["us_per_iteration"],
+                       "iterations": res["fp64"]["iters"], "converged": res["fp64"]["converged"]},
+        "fp32_error": {"vs": "FP64 marginals of the same graph and schedule (tol 1e-6)",
+                       "max_abs": float(np.abs(r["marginals"] - res["fp64"]["marginals"]).max())},
+        "roofline": _roofline_levels(r, "one iteration of the LEVELS executor (all kernels)"),
     }
 
 
@@ -360,7 +425,7 @@ def alarm_ranking(F, W, args):
                 dev_ms += st["device_ms"]
                 upd += st["message_updates"]
                 rounds += st["rounds"]
-                alg += st["algorithmic_bytes"]
+                alg += st["method_bytes"]
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         lv = g.schedule_levels().max() + 1 if sched == "seqfix" else 1
@@ -405,7 +470,7 @@ def alarm_cpu_baseline(w, budget_s: float):
     marg, m0, m1, st = oracle.bp_pairs(w, np.full(w.num_edges, 0.5), np.full(w.num_edges, 0.5),
                                        min(500, it_budget), 1e-6, 0.0, ranks=seq)
     dt = time.perf_counter() - t0
-    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle",
+    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle", **host_cpu(),
                 sample=f"the first round of the loop (SEQFIX, tol 1e-6, at most {min(500, it_budget)} iterations): "
                        f"{st['iterations']} iterations, {st['message_updates']} updates in {dt:.1f} s")
 
@@ -421,9 +486,55 @@ def cpu_baseline(w, budget_s: float):
     t0 = time.perf_counter()
     _, _, st = oracle.bp(w, max_iters=n, tol=0.0)
     dt = time.perf_counter() - t0
-    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle",
+    return dict(value=round(st["message_updates"] / dt, 1), unit="message updates/s", cores=1, kind="oracle", **host_cpu(),
                 sample=f"{n} full iterations (cold start, tol 0) of the same 200k-variable graph, forward-backward "
                        f"schedule and evidence as query 0: {st['message_updates']} updates in {dt:.1f} s")
+
+
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def serving_cpu_baseline(qs, runs, budget_s: float, n_prefix: int):
+    """The oracle (single thread) on a bounded sample of the serving stream: the cold runs of the
+    smallest graphs of the stream's first n_prefix graphs, same clamps, tol and iteration bound,
+    until about budget_s seconds are spent. Also the largest |FP32 marginal - oracle| over those runs
+    (the FP32 results of the batched server)."""
+    import oracle
+    order = sorted(range(min(n_prefix, len(qs))), key=lambda i: qs[i].graph.num_edges)
+    cold = {r["q"]: r for r in runs if r["warm"] == 0 and r["p1"] is not None}
+    t_all, upd, errs, errs_conv, names = 0.0, 0, [], [], []
+    for i in order:
+        if t_all >= budget_s:
+            break
+        q = qs[i]
+        ev = np.full(q.graph.num_vars, -1, dtype=np.int8)
+        ev[q.ev_vars] = q.ev_vals
+        t0 = time.perf_counter()
+        om, _, st = oracle.bp(q.graph, q.graph.max_iters, q.graph.tol, q.graph.damping, evidence=ev)
+        t_all += time.perf_counter() - t0
+        upd += st["message_updates"]
+        names.append(f"{q.graph.name}:{q.graph.num_vars}")
+        if i in cold:
+            e = float(np.abs(cold[i]["p1"] - om).max())
+            errs.append(e)
+            if st["converged"] and cold[i]["stats"]["converged"]:
+                errs_conv.append(e)
+    return dict(value=round(upd / t_all, 1), unit="message updates/s", cores=1, kind="oracle", **host_cpu(),
+                sample=f"cold runs of the {len(names)} smallest of the stream's first {n_prefix} graphs "
+                       f"({', '.join(names)}): {upd} updates in {t_all:.1f} s, single thread",
+                fp32_vs_oracle_max_abs=max(errs) if errs else None,
+                fp32_vs_oracle_max_abs_converged=max(errs_conv) if errs_conv else None,
+                runs_compared=len(errs))
 
 
 def pct(a, q):
@@ -437,7 +548,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=512, help="queries per batched step (512: two per compute unit)")
     ap.add_argument("--step-iters", type=int, default=8, help="iterations per server launch")
-    ap.add_argument("--fp64-queries", type=int, default=3)
+    ap.add_argument("--fp64-queries", type=int, default=3, help="smartfl: plain FP64 queries run one by one")
+    ap.add_argument("--fp64-graphs", type=int, default=48,
+                    help="serving: graphs of the stream's prefix served by the FIFO plain FP64 server")
     ap.add_argument("--max-iters", type=int, default=None, help="override the workload's 500")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
@@ -445,7 +558,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
     ap.add_argument("--alarms", type=int, default=300, help="alarms of the alarm-ranking workload")
     ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-terms", "bingo-large", "alarms"],
-                    default="smartfl",
+                    default="serving",
                     help="smartfl: batched queries of the 200k-variable SmartFL-shaped graph; serving: the "
                          "512-graph Poisson serving mix with warm re-queries; bingo: one 19M-edge "
                          "BINGO-shaped graph, flooding, 100 iterations (wide-level kernels); bingo-terms: the "
@@ -490,9 +603,18 @@ def main():
         print(json.dumps(bingo_large(F, W, args)), flush=True)
         return
     if args.workload == "serving":
-        rs = serving_mix(F, W, args)
-        kernel_s = rs["kernel_ms"] / 1e3
-        achieved = rs["algorithmic_bytes"] / kernel_s / 1e9
+        qs, runs, rs = serving_mix(F, W, args)
+        sd = rs["server"]
+        launches = max(1, sd["persistent_launches"])
+        avg_ms = sd["persistent_ms"] / launches
+        per_launch = sd["persistent_method_bytes"] / launches
+        achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        T = TRAFFIC_SERVING
+        traffic = None
+        if (args.queries == T["queries"] and args.batch == T["max_active"] and args.step_iters == T["step_iters"]
+                and args.seed == 0 and kernel_sources_sha256() == T["sources_sha256"]):
+            traffic = T["bytes_per_launch"]
+        p64 = rs["plain_fp64"]
         out = {
             "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
             "value": rs["mups"], "unit": "message updates/s", "n_gpus": 1, "steps": rs["runs"], "warmup": 0,
@@ -500,14 +622,27 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"serving_mix_{args.queries}_graphs_1k_500k_vars_poisson_200qps_warm_requery",
                        "seed": args.seed, "queries": args.queries, "runs": rs["runs"], "max_active": args.batch,
-                       "step_iters": args.step_iters, "max_iters": 100, "tol": 1e-6},
-            "serving_fp32": {k: v for k, v in rs.items() if k not in ("plain_fp64",)},
-            "plain_fp64": rs["plain_fp64"],
-            "batched_fp32_vs_plain_fp64": round(rs["mups"] / rs["plain_fp64"]["mups"], 2),
+                       "step_iters": args.step_iters, "max_iters": 100, "tol": 1e-6,
+                       "note": "a step is one query run (cold or warm re-query); value = f->v updates of all "
+                               "runs / wall time of the whole stream"},
+            "latency_ms": rs["latency"],
+            "serving_fp32": {k: v for k, v in rs.items() if k not in ("plain_fp64", "latency")},
+            "plain_fp64": p64,
+            "latency_fp32_vs_fp64_same_prefix": {"fp32": rs["prefix"]["latency"], "fp64": p64["latency"]},
+            "fp32_error": rs["fp32_error"],
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                         "kernel": "server steps (k_persistent + LEVELS kernels, concurrent)"},
+                         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                         "kernel": "k_persistent<PolLog32> (the narrow runs' launch of each server step)",
+                         "launches": sd["persistent_launches"], "avg_launch_ms": round(avg_ms, 4),
+                         "method_bytes_per_launch": per_launch,
+                         "kernel_share_of_device_ms": round(sd["persistent_ms"] / max(1e-9, sd["kernel_ms"]), 3),
+                         "bytes_note": "method bytes: per touched factor edge 4 + 3s, per written edge 2s (tol > 0), "
+                                       "s per NOISY_OR activation, s = 4 (FP32); times each run's iterations in the "
+                                       "launch; traffic: rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, copy-"
+                                       "calibrated, null unless the kernel sources match the profiled ones"},
         }
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = serving_cpu_baseline(qs, runs, args.cpu_budget, args.fp64_graphs)
         print(json.dumps(out), flush=True)
         return
     w = W.smartfl(args.seed)

@@ -120,11 +120,25 @@ typedef struct fastlbp_run_stats {
     int64_t contradictions;      /* messages replaced by uniform during the run */
     int32_t levels;              /* levels per iteration (dependency analysis) */
     int32_t executor;            /* FASTLBP_EXEC_LEVELS, _PERSISTENT or _HYBRID */
-    double algorithmic_bytes_per_iter; /* bytes one iteration must move at minimum: for every executed
-                                    * factor and variable task its structure, parameters, beliefs
-                                    * and messages read once, and every written message stored once */
+    double method_bytes_per_iter; /* bytes one iteration of the method moves at minimum, with s-byte
+                                    * messages (s = 4 FP32, 8 FP64): per edge of every factor a level
+                                    * touches 4 + 3s (its variable-major position, the f->v gathered
+                                    * for Eq.(1), the v->f written and read back), per written edge s
+                                    * (2s when damping or tol > 0 need the old value), s per NOISY_OR
+                                    * activation and per term weight, 2 bits per term indicator.
+                                    * Flooding: 4 + 5s per edge */
+    double impl_bytes_per_iter;   /* bytes this implementation's kernels read and write per
+                                    * iteration when every access goes to memory once: task records,
+                                    * structure, parameters, float64 beliefs per factor edge, messages */
     double device_ms;            /* device time of the run, HIP events on the handle's stream */
     int64_t message_updates;     /* factor-to-variable updates performed (edges x iterations) */
+    /* launch choices of the run (the library's defaults, or fastlbp_autotune's) */
+    int32_t thread_max_degree;   /* factors of degree <= this ran one per thread */
+    int32_t wave_max_degree;     /* then one per wavefront up to this degree, then one per workgroup */
+    int32_t var_thread_max_degree; /* variables of degree <= this ran one per thread, else per wavefront */
+    int32_t graph_iters;         /* iterations per hipGraph replay (LEVELS, HYBRID; 0 = the rule) */
+    int32_t persistent_threads;  /* workgroup size of the persistent executor (0 = the rule) */
+    int32_t tuned;               /* 1 if fastlbp_autotune set the handle's choices */
 } fastlbp_run_stats;
 
 typedef struct fastlbp_graph *fastlbp_graph_t;
@@ -165,6 +179,20 @@ int fastlbp_graph_create_terms(int32_t num_vars, int32_t num_factors, const int6
                                const int8_t *term_indicators, const fastlbp_options *opts, fastlbp_graph_t *out);
 
 void fastlbp_graph_destroy(fastlbp_graph_t g);
+
+/* Sizes and device memory of a handle. state_bytes: its own device state when resident (messages,
+ * beliefs, potentials, marginals, run state; what a server's memory budget counts); structure_bytes
+ * and plan_bytes: the graph structure and the current schedule's plan (shared with clones). */
+typedef struct fastlbp_graph_info {
+    int32_t num_vars, num_factors;
+    int64_t num_edges;
+    int32_t precision;
+    int32_t resident;          /* 1 while the device state is allocated, 0 while evicted by a server */
+    size_t state_bytes, structure_bytes, plan_bytes;
+    int32_t levels;            /* levels of the current schedule */
+    int32_t executed_levels;   /* levels holding non-PRIOR edges */
+} fastlbp_graph_info;
+int fastlbp_graph_get_info(fastlbp_graph_t g, fastlbp_graph_info *out);
 
 /* Creates a second handle on the same graph: it shares the device structure and the current
  * schedule with `src` (no copy) and has its own messages (uniform), evidence (none) and stream.
@@ -226,6 +254,47 @@ int fastlbp_graph_validate(int32_t num_vars, int32_t num_factors, const int64_t 
                            const double *edge_params);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Autotuning of the launch choices                                                              */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Launch choices for one graph shape, and how they were found. */
+typedef struct fastlbp_tune_result {
+    int32_t executor;              /* FASTLBP_EXEC_LEVELS, _PERSISTENT or _HYBRID */
+    int32_t thread_max_degree;     /* factors of degree <= this: one thread each (1..8) */
+    int32_t wave_max_degree;       /* then one wavefront each up to this degree (<= 257), then a workgroup */
+    int32_t var_thread_max_degree; /* variables of degree <= this: one thread each (<= 64), else a wavefront */
+    int32_t graph_iters;           /* iterations per hipGraph replay (LEVELS, HYBRID); 0 = the rule */
+    int32_t persistent_threads;    /* persistent workgroup size, 512 or 1024; 0 = the rule */
+    int32_t candidates;            /* configurations timed (0 when the choice came from the cache) */
+    int32_t from_cache;            /* 1 when the choice came from the cache file */
+    double best_ms_per_iter;       /* device time per iteration of the choice when it was timed */
+    double default_ms_per_iter;    /* the same for the library's default choice */
+    uint64_t key;                  /* shape key the choice is cached under */
+} fastlbp_tune_result;
+
+/* Picks the launch choices for the handle's graph and schedule. Small graphs lack parallelism and
+ * large ones are bound by memory (Section 5.2), so no fixed setting suits every shape: the tuner
+ * times a few candidates (executor; which factors run one per thread, per wavefront or per
+ * workgroup; which variables one per thread or per wavefront; iterations per hipGraph replay; the
+ * persistent workgroup size), each for probe_iters iterations with `damping` from the handle's
+ * current messages (restored after every probe), and puts the handle on the fastest. The choice is
+ * appended to the cache file (cache_path, or the environment variable FASTLBP_AUTOTUNE_CACHE; none:
+ * no caching) under a key of the graph's shape (sizes, degree histograms, level widths), and a
+ * later call for a handle of the same shape takes it from there without timing, so given the
+ * cache the choice is deterministic. Every choice computes the same messages up to floating-point
+ * rounding order. A later fastlbp_schedule_set keeps the bucket cut-offs; clones inherit the
+ * choices. out may be NULL. Errors: E_INVALID_ARG (probe_iters < 1, bad damping, cache not
+ * writable: the handle is tuned nevertheless), E_OOM, E_DEVICE (the handle is left as it was). */
+int fastlbp_autotune(fastlbp_graph_t g, int32_t probe_iters, double damping, const char *cache_path,
+                     fastlbp_tune_result *out);
+
+/* Host-only access to a tuning cache file (cache_path or FASTLBP_AUTOTUNE_CACHE). get: returns
+ * FASTLBP_OK and fills *out when the file has a valid line for key (the last one wins), 1 when not;
+ * put: appends r (which must name a valid executor and cut-offs). Errors: E_INVALID_ARG. */
+int fastlbp_autotune_cache_get(const char *cache_path, uint64_t key, fastlbp_tune_result *out);
+int fastlbp_autotune_cache_put(const char *cache_path, const fastlbp_tune_result *r);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Evidence (the feedback loop of Section 5.2.2) and messages                                   */
 /* ------------------------------------------------------------------------------------------ */
 
@@ -240,6 +309,36 @@ int fastlbp_evidence_clear(fastlbp_graph_t g);
  * message state, stopping early when an iteration's residual is below tol (tol = 0: never).
  * damping lambda in [0,1). stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
 int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
+
+/* Adaptive update strategies as rank generators (the randomized and residual-driven schedules of
+ * related work, Section 6). The run proceeds in blocks of `every` iterations (the last block may be
+ * shorter); before each block the generator gives every edge a rank, the dependency analysis splits
+ * the ranks into levels (as fastlbp_schedule_set(RANKED)), and the block runs from the messages the
+ * previous block left, as fastlbp_run with tol and damping; the run stops after a block that
+ * converged or after max_iters iterations in total.
+ *   FASTLBP_RANKS_RANDOM    random ordered groups: all edges of factor a get the rank
+ *                           SplitMix64(seed; counter block * 2^32 + a) mod groups, where SplitMix64
+ *                           is the published generator's output for that counter (the value mixed
+ *                           from seed + (counter + 1) * 0x9E3779B97F4A7C15)
+ *   FASTLBP_RANKS_RESIDUAL  residual-driven: block 0 is flooding; then each edge's rank comes from
+ *                           the change r_e of its message's P(x=1) over the previous block:
+ *                           rank = groups - 1 - min(groups - 1, floor(groups * r_e / max r)), so
+ *                           the largest changes are updated first (all rank 0 when nothing moved)
+ * The last block's schedule stays set. stats (may be NULL): iterations, updates, contradictions and
+ * device time summed over the blocks; the other fields from the last block. Errors: E_INVALID_ARG,
+ * E_OOM, E_DEVICE. */
+enum { FASTLBP_RANKS_RANDOM = 0, FASTLBP_RANKS_RESIDUAL = 1 };
+int fastlbp_run_adaptive(fastlbp_graph_t g, int32_t generator, int32_t groups, int32_t every, uint64_t seed,
+                         int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
+
+/* The two generators on the host, for callers that drive their own loop (and for checking):
+ * ranks_random writes the ranks of block `block` into edge_rank [E] (factor_offsets [F+1] as in
+ * fastlbp_graph_create); ranks_residual the ranks from two message states p_before, p_after [E] of
+ * P(x=1) in [0,1]. Errors: E_INVALID_ARG, E_BAD_GRAPH. */
+int fastlbp_ranks_random(int32_t num_factors, const int64_t *factor_offsets, int32_t groups, uint64_t seed,
+                         int32_t block, int32_t *edge_rank);
+int fastlbp_ranks_residual(int64_t num_edges, const double *p_before, const double *p_after, int32_t groups,
+                           int32_t *edge_rank);
 
 /* Runs n handles side by side in one launch of the persistent executor (one workgroup per
  * handle): each handle runs from its own message state and evidence, exactly as fastlbp_run with
@@ -275,7 +374,7 @@ typedef struct fastlbp_alarm_stats {
     int64_t message_updates;  /* factor-to-variable updates over all rounds */
     double device_ms;         /* device time of the BP runs and alarm picks (HIP events) */
     double wall_ms;           /* host wall time of the whole loop */
-    double algorithmic_bytes; /* algorithmic bytes of the BP runs (bytes per iteration x iterations) */
+    double method_bytes;      /* method bytes of the BP runs (method_bytes_per_iter x iterations) */
 } fastlbp_alarm_stats;
 
 /* The user-feedback loop of BINGO with a simulated user who knows the answers: each round runs
@@ -308,8 +407,11 @@ typedef struct fastlbp_server_options {
     int32_t precision;     /* FASTLBP_FP32 or FASTLBP_FP64; every submitted graph must use it */
     int32_t max_active;    /* runs advanced side by side (one workgroup each), >= 1 */
     int32_t step_iters;    /* iterations per step; requests join or leave between steps, >= 1 */
-    size_t memory_budget;  /* bytes of resident message state of the active graphs; 0 = 80% of the
-                              device's free memory at creation */
+    size_t memory_budget;  /* bytes of device state (messages, beliefs, potentials, marginals, run
+                              state) the server keeps resident for the graphs submitted to it: idle
+                              graphs are evicted to host memory to stay within it, evicted graphs
+                              are restored when admitted; 0 = 80% of the device's free memory at
+                              creation */
 } fastlbp_server_options;
 
 typedef struct fastlbp_server_stats {
@@ -319,9 +421,17 @@ typedef struct fastlbp_server_stats {
     double busy_ms;           /* wall time spent in steps */
     double kernel_ms;         /* device time of the steps (HIP events): per step, the longest of
                                * its persistent launch and the wide runs on their own streams */
-    double algorithmic_bytes; /* algorithmic bytes of the finished requests (bytes/iter x iters) */
+    double method_bytes;      /* method bytes of the finished requests (method_bytes_per_iter x iterations) */
     double p50_ms, p99_ms;    /* latency (submit to marginals ready) of the finished requests */
     int32_t pending, active;  /* queue length and runs in flight right now */
+    int64_t evictions;        /* idle graphs whose device state was moved to host memory */
+    int64_t restores;         /* evicted graphs whose device state was allocated again at admission */
+    size_t resident_bytes;    /* device state of the server's graphs resident now */
+    size_t peak_resident_bytes; /* largest resident_bytes after an admission round */
+    int64_t persistent_launches; /* launches of the persistent executor (one per step with narrow runs) */
+    double persistent_ms;     /* their device time (HIP events on the server's stream) */
+    double persistent_method_bytes; /* their method bytes: each run's method_bytes_per_iter times the
+                               * iterations it advanced in the launch */
 } fastlbp_server_stats;
 
 /* Defaults: device 0, FP32, 256 active runs, 2 iterations per step, budget 0 (80% of free). */

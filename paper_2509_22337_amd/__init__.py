@@ -54,8 +54,11 @@ class ServerOptions(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("message_updates", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("busy_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("algorithmic_bytes", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("pending", ctypes.c_int32), ("active", ctypes.c_int32)]
+                ("method_bytes", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("evictions", ctypes.c_int64),
+                ("restores", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t),
+                ("peak_resident_bytes", ctypes.c_size_t), ("persistent_launches", ctypes.c_int64),
+                ("persistent_ms", ctypes.c_double), ("persistent_method_bytes", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -64,8 +67,33 @@ class ServerStats(ctypes.Structure):
 class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("contradictions", ctypes.c_int64), ("levels", ctypes.c_int32), ("executor", ctypes.c_int32),
-                ("algorithmic_bytes_per_iter", ctypes.c_double), ("device_ms", ctypes.c_double),
-                ("message_updates", ctypes.c_int64)]
+                ("method_bytes_per_iter", ctypes.c_double), ("impl_bytes_per_iter", ctypes.c_double),
+                ("device_ms", ctypes.c_double),
+                ("message_updates", ctypes.c_int64), ("thread_max_degree", ctypes.c_int32),
+                ("wave_max_degree", ctypes.c_int32), ("var_thread_max_degree", ctypes.c_int32),
+                ("graph_iters", ctypes.c_int32), ("persistent_threads", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("num_vars", ctypes.c_int32), ("num_factors", ctypes.c_int32), ("num_edges", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("resident", ctypes.c_int32), ("state_bytes", ctypes.c_size_t),
+                ("structure_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t), ("levels", ctypes.c_int32),
+                ("executed_levels", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("executor", ctypes.c_int32), ("thread_max_degree", ctypes.c_int32),
+                ("wave_max_degree", ctypes.c_int32), ("var_thread_max_degree", ctypes.c_int32),
+                ("graph_iters", ctypes.c_int32), ("persistent_threads", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("best_ms_per_iter", ctypes.c_double), ("default_ms_per_iter", ctypes.c_double),
+                ("key", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -74,7 +102,7 @@ class RunStats(ctypes.Structure):
 class AlarmStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("true_found", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("message_updates", ctypes.c_int64), ("device_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-                ("algorithmic_bytes", ctypes.c_double)]
+                ("method_bytes", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -88,7 +116,9 @@ EXPORTS = [
     "fastlbp_evidence_clear", "fastlbp_run", "fastlbp_marginals", "fastlbp_messages_get", "fastlbp_messages_set",
     "fastlbp_messages_reset", "fastlbp_last_error", "fastlbp_version", "fastlbp_server_options_default",
     "fastlbp_server_create", "fastlbp_server_submit", "fastlbp_server_poll", "fastlbp_server_wait",
-    "fastlbp_server_get_stats", "fastlbp_server_destroy", "fastlbp_alarm_loop",
+    "fastlbp_server_get_stats", "fastlbp_server_destroy", "fastlbp_alarm_loop", "fastlbp_autotune",
+    "fastlbp_autotune_cache_get", "fastlbp_autotune_cache_put", "fastlbp_graph_get_info", "fastlbp_run_adaptive",
+    "fastlbp_ranks_random", "fastlbp_ranks_residual",
 ]
 
 _lib = None
@@ -129,6 +159,13 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_evidence_clear.argtypes = [P]
     lib.fastlbp_run.argtypes = [P, i32, f64, f64, ctypes.POINTER(RunStats)]
     lib.fastlbp_marginals.argtypes = [P, P]
+    lib.fastlbp_graph_get_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
+    lib.fastlbp_run_adaptive.argtypes = [P, i32, i32, i32, ctypes.c_uint64, i32, f64, f64, ctypes.POINTER(RunStats)]
+    lib.fastlbp_ranks_random.argtypes = [i32, P, i32, ctypes.c_uint64, i32, P]
+    lib.fastlbp_ranks_residual.argtypes = [i64, P, P, i32, P]
+    lib.fastlbp_autotune.argtypes = [P, i32, f64, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+    lib.fastlbp_autotune_cache_get.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(TuneResult)]
+    lib.fastlbp_autotune_cache_put.argtypes = [ctypes.c_char_p, ctypes.POINTER(TuneResult)]
     lib.fastlbp_alarm_loop.argtypes = [P, i32, P, P, i32, i32, f64, f64, P, P, ctypes.POINTER(AlarmStats)]
     lib.fastlbp_messages_get.argtypes = [P, P]
     lib.fastlbp_messages_set.argtypes = [P, P]
@@ -203,6 +240,48 @@ def classes_to_ranks(num_vars, fac_off, edge_var, fac_type, edge_class, num_clas
     out = np.zeros(len(ev), dtype=np.int32)
     _check(load().fastlbp_classes_to_ranks(int(num_vars), len(fo) - 1, _p(fo), _p(ev), _p(ft), int(num_classes),
                                            _p(ec), len(ar), _p(ar) if len(ar) else None, _p(out)))
+    return out
+
+
+def _path(p):
+    return None if p is None else str(p).encode()
+
+
+def autotune_cache_get(path, key: int):
+    """The cached launch choice for a shape key (dict), or None."""
+    r = TuneResult()
+    rc = load().fastlbp_autotune_cache_get(_path(path), ctypes.c_uint64(key), ctypes.byref(r))
+    if rc == 1:
+        return None
+    _check(rc)
+    return r.as_dict()
+
+
+def autotune_cache_put(path, result: "TuneResult") -> None:
+    _check(load().fastlbp_autotune_cache_put(_path(path), ctypes.byref(result)))
+
+
+RANKS_RANDOM, RANKS_RESIDUAL = 0, 1
+
+
+def ranks_random(fac_off, groups: int, seed: int, block: int) -> np.ndarray:
+    """Random ordered groups for one block (fastlbp_ranks_random): every factor's edges share a rank
+    in [0, groups) from SplitMix64 of the seed, block and factor."""
+    fo = np.ascontiguousarray(fac_off, dtype=np.int64)
+    out = np.zeros(int(fo[-1]), dtype=np.int32)
+    _check(load().fastlbp_ranks_random(len(fo) - 1, _p(fo), int(groups), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                       int(block), _p(out)))
+    return out
+
+
+def ranks_residual(p_before, p_after, groups: int) -> np.ndarray:
+    """Residual-driven ranks (fastlbp_ranks_residual): the edges whose P(x=1) changed most go first."""
+    b = np.ascontiguousarray(p_before, dtype=np.float64)
+    a = np.ascontiguousarray(p_after, dtype=np.float64)
+    if len(a) != len(b):
+        raise FastLBPError(E_INVALID_ARG, "two message states of one length")
+    out = np.zeros(len(a), dtype=np.int32)
+    _check(load().fastlbp_ranks_residual(len(a), _p(b), _p(a), int(groups), _p(out)))
     return out
 
 
@@ -388,6 +467,29 @@ class Graph:
         st = RunStats()
         _check(load().fastlbp_run(self._h, int(max_iters), float(tol), float(damping), ctypes.byref(st)))
         return st.as_dict()
+
+    def run_adaptive(self, generator: str, groups: int, every: int, seed: int, max_iters: int, tol: float = 0.0,
+                     damping: float = 0.0) -> dict:
+        """fastlbp_run_adaptive: blocks of `every` iterations, each on the schedule the generator
+        ("random" ordered groups or "residual"-driven ranks) draws before it."""
+        gen = {"random": RANKS_RANDOM, "residual": RANKS_RESIDUAL}[generator]
+        st = RunStats()
+        _check(load().fastlbp_run_adaptive(self._h, gen, int(groups), int(every), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                           int(max_iters), float(tol), float(damping), ctypes.byref(st)))
+        return st.as_dict()
+
+    def info(self) -> dict:
+        """Sizes, residency and device memory of the handle (fastlbp_graph_get_info)."""
+        r = GraphInfo()
+        _check(load().fastlbp_graph_get_info(self._h, ctypes.byref(r)))
+        return r.as_dict()
+
+    def autotune(self, probe_iters: int = 4, damping: float = 0.0, cache_path=None) -> dict:
+        """fastlbp_autotune: time a few launch choices on this graph and schedule, keep the fastest
+        (cached under the graph's shape key in cache_path or FASTLBP_AUTOTUNE_CACHE)."""
+        r = TuneResult()
+        _check(load().fastlbp_autotune(self._h, int(probe_iters), float(damping), _path(cache_path), ctypes.byref(r)))
+        return r.as_dict()
 
     def marginals(self) -> np.ndarray:
         out = np.zeros(self.num_vars)

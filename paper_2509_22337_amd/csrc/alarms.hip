@@ -107,6 +107,7 @@ int fastlbp_alarm_loop(fastlbp_graph_t g, int32_t A, const int32_t *alarm_vars, 
         set_error("need max_iters >= 0, tol >= 0, 0 <= damping < 1");
         return FASTLBP_E_INVALID_ARG;
     }
+    std::lock_guard<std::recursive_mutex> lk(graph_mutex(g));
     const auto t0 = std::chrono::steady_clock::now();
     fastlbp_alarm_stats st{};
     const Alloc &al = graph_alloc(g);
@@ -117,6 +118,7 @@ int fastlbp_alarm_loop(fastlbp_graph_t g, int32_t A, const int32_t *alarm_vars, 
     int rc = FASTLBP_OK;
     try {
         ALCHK(hipSetDevice(graph_device(g)));
+        graph_restore(g);
         hipStream_t s = graph_stream(g);
         d_vars = (int32_t *)al.get(sizeof(int32_t) * size_t(A));
         d_insp = (int8_t *)al.get(size_t(A));
@@ -135,7 +137,7 @@ int fastlbp_alarm_loop(fastlbp_graph_t g, int32_t A, const int32_t *alarm_vars, 
             st.iterations += rs.iterations;
             st.message_updates += rs.message_updates;
             st.device_ms += rs.device_ms;
-            st.algorithmic_bytes += rs.algorithmic_bytes_per_iter * double(rs.iterations);
+            st.method_bytes += rs.method_bytes_per_iter * double(rs.iterations);
             ALCHK(hipEventRecord(e0, s));
             refresh_beliefs(g);  // the marginals of Eq.(3) exactly as fastlbp_marginals reports them
             k_alarm_pick<<<1, kPickThreads, 0, s>>>(graph_beliefs(g), d_vars, d_insp, A, d_pick);

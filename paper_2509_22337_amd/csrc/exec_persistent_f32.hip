@@ -1,0 +1,10 @@
+// Persistent executor instantiated for float32 log-domain messages.
+#include "exec.h"
+
+namespace fastlbp {
+
+void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
+    launch_persistent<PolLog32>(lc, n, gs, damping, step);
+}
+
+}  // namespace fastlbp

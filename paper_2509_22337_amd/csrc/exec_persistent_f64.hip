@@ -1,0 +1,10 @@
+// Persistent executor instantiated for float64 messages.
+#include "exec.h"
+
+namespace fastlbp {
+
+void persistent_launch_f64(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
+    launch_persistent<PolLin64>(lc, n, gs, damping, step);
+}
+
+}  // namespace fastlbp

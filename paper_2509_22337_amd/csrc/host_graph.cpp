@@ -1,5 +1,6 @@
 // Host-side graph preparation (the Initialization and Dependency Analysis stages of Section 4.1).
 #include <algorithm>
+#include <array>
 #include <functional>
 #include <queue>
 #include <cmath>
@@ -440,14 +441,15 @@ void HostGraph::set_terms(const int64_t *toff, const double *tw, const int8_t *t
     }
 }
 
-int factor_bucket(int deg) {
-    if (deg <= kThreadMaxDeg) return FB_THREAD;
-    if (deg <= kWaveMaxDeg) return FB_WAVE;
+int factor_bucket(int deg, const PlanParams &pp) {
+    if (deg <= pp.thread_max_deg) return FB_THREAD;
+    if (deg <= pp.wave_max_deg) return FB_WAVE;
     return FB_BLOCK;
 }
 
 void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int32_t nlevels, bool flooding,
-                     int msg_bytes, int param_bytes) {
+                     int msg_bytes, int param_bytes, const PlanParams &pp) {
+    params = pp;
     num_levels = nlevels;
     level_of_edge = level;
     all_active = flooding ? 1 : 0;
@@ -471,11 +473,12 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     std::vector<std::vector<int32_t>> var_by_level(VB_COUNT * std::max(exec_levels, 1));
     bytes_per_iter = 0.0;
     updates_per_iter = 0;
+    touched_edges_per_iter = noisy_params_per_iter = term_weights_per_iter = term_entries_per_iter = 0;
     for (int32_t a = 0; a < g.F; ++a) {
         if (g.fac_type[a] == FASTLBP_PRIOR) continue;
         int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
         const bool terms = g.fac_type[a] == FASTLBP_TERMS;
-        int bucket = terms ? (d <= kThreadMaxDeg ? FB_TERMS_THREAD : FB_TERMS_WAVE) : factor_bucket(int(d));
+        int bucket = terms ? (d <= kThreadMaxDeg ? FB_TERMS_THREAD : FB_TERMS_WAVE) : factor_bucket(int(d), pp);
         int32_t prev = -1;
         // levels of a factor's edges in ascending order of level, each level once
         std::vector<int32_t> lv;
@@ -485,6 +488,12 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             if (L == prev) continue;
             prev = L;
             fac_by_level[L * FB_COUNT + bucket].push_back(a);
+            touched_edges_per_iter += d;
+            if (g.fac_type[a] == FASTLBP_NOISY_OR) noisy_params_per_iter += d - 1;
+            if (terms) {
+                term_weights_per_iter += g.term_off[a + 1] - g.term_off[a];
+                term_entries_per_iter += int64_t(g.term_off[a + 1] - g.term_off[a]) * d;
+            }
             // bytes of a factor task: offsets, type, parameters, list entry; per edge: variable id,
             // belief, old message, (level tag unless flooding), NOISY_OR activation
             double per_edge = 4.0 + sizeof(Belief) + msg_bytes + (flooding ? 0 : 4) +
@@ -505,7 +514,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         ++updates_per_iter;
         bytes_per_iter += msg_bytes;  // written message
         int32_t v = g.edge_var[e];
-        int vb = g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE;
+        int vb = g.var_deg[v] <= pp.var_thread_max_deg ? VB_THREAD : VB_WAVE;
         var_by_level[L * VB_COUNT + vb].push_back(v);
     }
     for (auto &lst : var_by_level) {
@@ -558,7 +567,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         }
         init_var[b].clear();
     }
-    for (int32_t v = 0; v < g.V; ++v) init_var[g.var_deg[v] <= kVarThreadMaxDeg ? VB_THREAD : VB_WAVE].push_back(v);
+    for (int32_t v = 0; v < g.V; ++v) init_var[g.var_deg[v] <= pp.var_thread_max_deg ? VB_THREAD : VB_WAVE].push_back(v);
     // records: factor {b, d | type << 8 | active << 16, id, u0..u7, 0}; variable {v, row, degree,
     // e0..e4}. A degree group is padded to a multiple of 64 with copies of its first record that
     // write nothing (factor: no active edge; variable: padding flag).
@@ -636,6 +645,83 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             trec.insert(trec.end(), r, r + 12);
         }
         trec_off.push_back(int32_t(trec.size() / 12));
+    }
+    // incremental variable phase (LEVELS executor): which (level, variable) tasks write only part
+    // of the variable's edges; the written edges of every level grouped by variable
+    {
+        std::vector<int64_t> lcnt(size_t(exec_levels) + 1, 0);
+        for (int64_t e = 0; e < g.E; ++e)
+            if (edge_exec_level[e] >= 0) lcnt[size_t(edge_exec_level[e]) + 1]++;
+        for (int32_t L = 0; L < exec_levels; ++L) lcnt[size_t(L) + 1] += lcnt[size_t(L)];
+        std::vector<int64_t> pos(lcnt.begin(), lcnt.end() - 1);
+        std::vector<int32_t> by_level(static_cast<size_t>(lcnt[size_t(exec_levels)]));
+        for (int64_t e = 0; e < g.E; ++e)
+            if (edge_exec_level[e] >= 0) by_level[size_t(pos[size_t(edge_exec_level[e])]++)] = int32_t(e);
+        has_delta = 0;
+        for (int32_t L = 0; L < exec_levels && !has_delta; ++L) {
+            auto b = by_level.begin() + lcnt[size_t(L)], en = by_level.begin() + lcnt[size_t(L) + 1];
+            std::stable_sort(b, en, [&](int32_t x, int32_t y) { return g.edge_var[x] < g.edge_var[y]; });
+            for (auto it = b; it != en;) {
+                auto jt = it;
+                while (jt != en && g.edge_var[*jt] == g.edge_var[*it]) ++jt;
+                if (int32_t(jt - it) < g.var_deg[g.edge_var[*it]]) has_delta = 1;
+                it = jt;
+            }
+        }
+        drec.clear();
+        dedge.clear();
+        dwave.clear();
+        drec_off.assign(1, 0);
+        dwave_off.assign(1, 0);
+        for (int32_t L = 0; has_delta && L < exec_levels; ++L) {
+            auto b = by_level.begin() + lcnt[size_t(L)], en = by_level.begin() + lcnt[size_t(L) + 1];
+            std::stable_sort(b, en, [&](int32_t x, int32_t y) { return g.edge_var[x] < g.edge_var[y]; });
+            // records of the level, then sorted by (kind, edges held) so a wavefront runs one shape
+            std::vector<std::array<int32_t, 8>> recs;
+            for (auto it = b; it != en;) {
+                auto jt = it;
+                const int32_t v = g.edge_var[*it];
+                while (jt != en && g.edge_var[*jt] == v) ++jt;
+                const int32_t w = int32_t(jt - it), deg = g.var_deg[v];
+                std::array<int32_t, 8> r{};
+                r[0] = v;
+                if (w == deg && deg <= pp.var_thread_max_deg) {  // rebuild from the row
+                    r[1] = g.var_off[v];
+                    r[2] = deg;
+                    for (int q = 0; q < kVarRecEdges; ++q) r[3 + q] = q < deg ? g.var_edge[g.var_off[v] + q] : 0;
+                    recs.push_back(r);
+                } else if (w <= kVarThreadMaxDeg && w < deg) {  // add new - old of the written edges
+                    r[1] = int32_t(dedge.size());
+                    r[2] = w | (1 << 29);
+                    for (int q = 0; q < w; ++q) {
+                        if (q < kVarRecEdges) r[3 + q] = *(it + q);
+                        dedge.push_back(*(it + q));
+                    }
+                    recs.push_back(r);
+                } else {
+                    dwave.push_back(v);  // many written edges of a high-degree variable: rebuild by wavefront
+                }
+                it = jt;
+            }
+            auto key = [](const std::array<int32_t, 8> &r) {
+                return ((r[2] >> 29) & 1) * 16 + std::min<int32_t>(r[2] & 0xffff, kVarRecEdges);
+            };
+            std::stable_sort(recs.begin(), recs.end(),
+                             [&](const std::array<int32_t, 8> &x, const std::array<int32_t, 8> &y) { return key(x) < key(y); });
+            for (size_t i = 0; i < recs.size();) {
+                size_t j = i;
+                while (j < recs.size() && key(recs[j]) == key(recs[i])) ++j;
+                for (size_t k = i; k < j; ++k) drec.insert(drec.end(), recs[k].begin(), recs[k].end());
+                for (size_t k = j - i; k % 64; ++k) {  // padding copies of the group's first record
+                    std::array<int32_t, 8> p = recs[i];
+                    p[2] |= 1 << 30;
+                    drec.insert(drec.end(), p.begin(), p.end());
+                }
+                i = j;
+            }
+            drec_off.push_back(int32_t(drec.size() / 8));
+            dwave_off.push_back(int32_t(dwave.size()));
+        }
     }
     // staging in LDS: a level qualifies when all of its written edges come from thread-bucket
     // factors, its variables have at most kStagedEdges written edges each and none takes the
@@ -798,5 +884,77 @@ extern "C" int fastlbp_classes_to_ranks(int32_t num_vars, int32_t num_factors, c
                                    edge_class, num_arcs, arcs, rank);
     if (rc) return rc;
     if (!rank.empty()) std::memcpy(edge_rank, rank.data(), sizeof(int32_t) * rank.size());
+    return FASTLBP_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Rank generators of adaptive update strategies (randomized and residual-driven BP, Section 6)
+// ------------------------------------------------------------------------------------------------
+
+namespace fastlbp {
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", 2014): the
+// value for counter x of a stream is the output mix of seed + (x + 1) * golden gamma.
+uint64_t splitmix64_at(uint64_t seed, uint64_t x) {
+    uint64_t z = seed + (x + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void ranks_random(int32_t F, const int64_t *off, int32_t groups, uint64_t seed, int32_t block, int32_t *rank) {
+    for (int32_t a = 0; a < F; ++a) {
+        const uint64_t x = (uint64_t(uint32_t(block)) << 32) | uint64_t(uint32_t(a));
+        const int32_t r = int32_t(splitmix64_at(seed, x) % uint64_t(groups));
+        for (int64_t e = off[a]; e < off[a + 1]; ++e) rank[e] = r;
+    }
+}
+
+void ranks_residual(int64_t E, const double *before, const double *after, int32_t groups, int32_t *rank) {
+    double rmax = 0.0;
+    for (int64_t e = 0; e < E; ++e) rmax = std::max(rmax, std::fabs(after[e] - before[e]));
+    for (int64_t e = 0; e < E; ++e) {
+        if (!(rmax > 0.0)) {
+            rank[e] = 0;
+            continue;
+        }
+        const double q = double(groups) * (std::fabs(after[e] - before[e]) / rmax);
+        const int32_t bucket = std::min<int32_t>(groups - 1, int32_t(std::floor(q)));
+        rank[e] = groups - 1 - bucket;  // the largest changes go first
+    }
+}
+
+}  // namespace fastlbp
+
+extern "C" int fastlbp_ranks_random(int32_t num_factors, const int64_t *factor_offsets, int32_t groups, uint64_t seed,
+                                    int32_t block, int32_t *edge_rank) {
+    fastlbp::clear_error();
+    if (num_factors < 0 || !factor_offsets || groups < 1 || block < 0 ||
+        (factor_offsets[num_factors] > 0 && !edge_rank)) {
+        fastlbp::set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    for (int32_t a = 0; a < num_factors; ++a)
+        if (factor_offsets[a + 1] < factor_offsets[a]) {
+            fastlbp::set_error("factor_offsets must be non-decreasing");
+            return FASTLBP_E_BAD_GRAPH;
+        }
+    fastlbp::ranks_random(num_factors, factor_offsets, groups, seed, block, edge_rank);
+    return FASTLBP_OK;
+}
+
+extern "C" int fastlbp_ranks_residual(int64_t num_edges, const double *p_before, const double *p_after, int32_t groups,
+                                      int32_t *edge_rank) {
+    fastlbp::clear_error();
+    if (num_edges < 0 || groups < 1 || (num_edges > 0 && (!p_before || !p_after || !edge_rank))) {
+        fastlbp::set_error("invalid argument");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    for (int64_t e = 0; e < num_edges; ++e)
+        if (!(p_before[e] >= 0.0 && p_before[e] <= 1.0) || !(p_after[e] >= 0.0 && p_after[e] <= 1.0)) {
+            fastlbp::set_error("message " + std::to_string(e) + " outside [0,1]");
+            return FASTLBP_E_INVALID_ARG;
+        }
+    fastlbp::ranks_residual(num_edges, p_before, p_after, groups, edge_rank);
     return FASTLBP_OK;
 }

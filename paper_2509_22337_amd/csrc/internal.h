@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "fastlbp.h"
@@ -67,7 +68,7 @@ void marginals_into(fastlbp_graph *g, double *p1);
 // Rebuilds every belief from phi and the current messages (the executors may leave beliefs that
 // were updated incrementally during the last level), on the handle's stream, without waiting.
 void refresh_beliefs(fastlbp_graph *g);
-void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms);
+void fill_stats_public(fastlbp_graph *g, fastlbp_run_stats &s, float ms, double damping);
 int set_evidence(fastlbp_graph *g, int32_t n, const int32_t *vars, const int8_t *values);
 int graph_device(fastlbp_graph *g);
 int graph_precision(fastlbp_graph *g);
@@ -77,5 +78,20 @@ void graph_sync(fastlbp_graph *g);
 hipStream_t graph_stream(fastlbp_graph *g);
 const Belief *graph_beliefs(fastlbp_graph *g);
 const Alloc &graph_alloc(fastlbp_graph *g);
+// Residency of a handle's device state (messages, beliefs, potentials, run state): graph_evict
+// copies the messages to host memory and frees the state, graph_restore allocates it again and
+// puts the messages back (exact bytes, so a warm start survives). graph_mutex is held by every
+// public call on the handle; a server evicting an idle handle takes it with try_lock.
+void graph_evict(fastlbp_graph *g);
+void graph_restore(fastlbp_graph *g);
+bool graph_resident(fastlbp_graph *g);
+std::recursive_mutex &graph_mutex(fastlbp_graph *g);
+// Called by fastlbp_graph_destroy for a handle a server manages: the server drops it from its set.
+void server_forget(fastlbp_server *s, fastlbp_graph *g);
+void graph_set_manager(fastlbp_graph *g, fastlbp_server *s);
+fastlbp_server *graph_manager(fastlbp_graph *g);
+uint64_t &graph_last_use(fastlbp_graph *g);
+// Method bytes of one iteration of the handle's schedule (fastlbp_run_stats.method_bytes_per_iter).
+double graph_method_bytes_per_iter(fastlbp_graph *g, double tol, double damping);
 
 }  // namespace fastlbp

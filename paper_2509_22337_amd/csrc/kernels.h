@@ -232,11 +232,18 @@ __device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S
     return l;
 }
 
+// Stores a new message, and its old value where the plan's variable tasks add new - old.
+template <class S, class V>
+__device__ __forceinline__ void put_msg(const DevGraph<S, V> &g, int32_t e, S nw, S old) {
+    g.msg[e] = nw;
+    if (g.prev.p) g.prev[e] = old;
+}
+
 template <class P, bool DAMP>
 __device__ __forceinline__ void store_msg(const DevGraph<typename P::S, typename P::V> &g, int32_t e,
                                           typename P::S old, typename P::V o0, typename P::V o1, bool force_contra,
                                           Acc &acc) {
-    g.msg[e] = finish_msg<P, DAMP>(g, old, o0, o1, force_contra, acc);
+    put_msg(g, e, finish_msg<P, DAMP>(g, old, o0, o1, force_contra, acc), old);
 }
 
 template <bool ALL_ACTIVE>
@@ -717,7 +724,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
                 V m0, m1;
                 P::leaf(-vf[1 - k], m0, m1);
                 const S l = finish_msg<P, DAMP>(g, lo[k], m0, m1, nl[1 - k], acc);
-                g.msg[b + k] = l;
+                put_msg(g, b + k, l, lo[k]);
                 stage_slot<P>(slots, slot0, active, k, l, lo[k]);
             }
             return;
@@ -748,7 +755,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
         V o0, o1;
         head_msg<P>(type, tot, fp, o0, o1);
         const S l = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
-        g.msg[b + n] = l;
+        put_msg(g, b + n, l, lo[n]);
         stage_slot<P>(slots, slot0, active, n, l, lo[n]);
     }
     HF<V> sx[n];
@@ -767,7 +774,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
             input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
             int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
             const S l = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
-            g.msg[b + k] = l;
+            put_msg(g, b + k, l, lo[k]);
             stage_slot<P>(slots, slot0, active, k, l, lo[k]);
         }
         run = combine<P>(run, lf[k]);
@@ -872,6 +879,43 @@ __device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
         B.nneg--;
     else
         B.fin -= (double)l;
+}
+
+// Incremental variable task (LEVELS executor), from a record of the level's delta list: kind 0
+// rebuilds the belief from the whole row as var_rec does; kind 1 takes the belief before the level
+// and, for each message the level wrote, subtracts its old value (prev) and adds the new one. The
+// counts of infinite terms stay exact; the finite part is updated in float64 (beliefs are rebuilt
+// from the messages at the start of every run). Padding records (bit 30) store nothing.
+template <class P>
+__device__ __forceinline__ void var_delta(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
+                                          const VarRec &r) {
+    if (!((r.cnt >> 29) & 1)) {
+        var_rec<P>(g, r);
+        return;
+    }
+    using S = typename P::S;
+    const int n = r.cnt & 0xffff;
+    const bool pad = (r.cnt >> 30) & 1;
+    Belief B = g.bel.ld(r.v);
+    S nw[kVarRecEdges], od[kVarRecEdges];
+#pragma unroll
+    for (int j = 0; j < kVarRecEdges; ++j) {
+        const int32_t e = r.e[j < n ? j : 0];
+        nw[j] = g.msg[e];
+        od[j] = g.prev[e];
+    }
+#pragma unroll
+    for (int j = 0; j < kVarRecEdges; ++j)
+        if (j < n) {
+            belief_sub<P>(B, od[j]);
+            belief_add<P>(B, nw[j]);
+        }
+    for (int32_t j = kVarRecEdges; j < n; ++j) {
+        const int32_t e = plan.dedge[r.start + j];
+        belief_sub<P>(B, g.prev[e]);
+        belief_add<P>(B, g.msg[e]);
+    }
+    if (!pad) g.bel.st(r.v, B);
 }
 
 // Variable task of a staged level: its belief before the level (left in bslots by the factor that

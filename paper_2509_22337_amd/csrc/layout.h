@@ -132,6 +132,8 @@ struct DevGraph {
     GPtr<const Belief> phi;         // [V] priors + evidence
     GPtr<Belief> bel;               // [V]
     GPtr<S> msg;                    // [E]
+    GPtr<S> prev;                   // [E] value a written message had before the level (plans with
+                                    // incremental variable tasks), else null
     GPtr<const int32_t> edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
     // weighted-term factors: term range per factor [F+1], weights in the value domain [T], start of
     // each factor's indicator rows [F+1], indicators (row t of factor a: one entry per edge, -1 any)
@@ -205,6 +207,14 @@ struct DevPlan {
     GPtr<const TermRec> trec;
     GPtr<const int32_t> trec_off;   // [num_levels+1]
     int32_t stage_slots;            // most slots any staged level uses (0: none staged)
+    // incremental variable tasks of the LEVELS executor (has_delta): per level records and the
+    // wavefront rebuilds of high-degree variables
+    int32_t has_delta;
+    GPtr<const VarRec> drec;
+    GPtr<const int32_t> drec_off;   // [num_levels+1]
+    GPtr<const int32_t> dedge;      // written edges of the delta records beyond the fifth
+    GPtr<const int32_t> dwave;
+    GPtr<const int32_t> dwave_off;  // [num_levels+1]
 };
 
 }  // namespace fastlbp

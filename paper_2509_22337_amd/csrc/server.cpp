@@ -1,14 +1,21 @@
 // Continuous-batching query server (the interactive feedback loop of Section 5.2.2 at scale).
 //
 // A request is a graph handle plus evidence clamps and run parameters. One host thread runs the
-// loop: admit waiting requests while the number of active runs stays within max_active and the
-// resident state of the active graphs within the memory budget (a graph with a request in flight
-// is not admitted twice: its messages are one state), advance every active run by step_iters
-// iterations in one persistent launch (one workgroup per run, so the runs overlap on the device;
-// runs whose levels are too wide for one workgroup take the LEVELS executor on their own stream,
-// concurrently with that launch), then retire the runs that finished and copy their marginals out. Requests that arrive while a
-// step runs join at the next step. Messages stay resident in the handle, so a re-query after new
-// evidence starts warm.
+// loop: admit waiting requests in arrival order while the number of active runs stays within
+// max_active and the device state of the server's graphs within the memory budget (a graph with a
+// request in flight is not admitted twice: its messages are one state), advance every active run
+// by step_iters iterations in one persistent launch (one workgroup per run, so the runs overlap on
+// the device; runs whose levels are too wide for one workgroup take the LEVELS executor on their
+// own stream, concurrently with that launch), then retire the runs that finished and copy their
+// marginals out. Requests that arrive while a step runs join at the next step.
+//
+// Device memory. Every graph submitted to the server is managed by it: the server counts the
+// device state (messages, beliefs, potentials, marginals, run state) of those that are resident.
+// Admitting a request whose graph is evicted allocates its state again and restores its messages;
+// when that, or the graphs already resident, would exceed the budget, the server first evicts idle
+// graphs (no request in flight), least recently used first: their messages go to host memory
+// (exact bytes) and their device state is freed. A re-query after new evidence therefore starts
+// warm whether its graph stayed resident or was evicted in between.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -20,6 +27,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "fastlbp.h"
@@ -56,18 +64,60 @@ struct fastlbp_server {
     std::vector<std::shared_ptr<Request>> active;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
     std::unordered_map<fastlbp_graph *, int> runs_of_graph;  // completed runs per handle (warm starts)
+    std::unordered_set<fastlbp_graph *> managed;             // graphs submitted here (residency managed)
+    uint64_t clock = 0;                                       // least-recently-used stamps
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread th;
-    size_t resident = 0;
     // statistics
     std::vector<double> lat_ms;
-    int64_t completed = 0, updates = 0, steps = 0;
-    double busy_ms = 0.0, kernel_ms = 0.0, alg_bytes = 0.0;
+    int64_t completed = 0, updates = 0, steps = 0, evictions = 0, restores = 0;
+    size_t peak_resident = 0;
+    int64_t persistent_launches = 0;
+    double busy_ms = 0.0, kernel_ms = 0.0, method_bytes = 0.0, persistent_ms = 0.0, persistent_bytes = 0.0;
     Clock::time_point t0 = Clock::now();
 
     void loop();
+    size_t resident_bytes() const {
+        size_t t = 0;
+        for (auto *g : managed)
+            if (graph_resident(g)) t += graph_state_bytes(g);
+        return t;
+    }
+    bool is_active(const fastlbp_graph *g) const {
+        for (auto &a : active)
+            if (a->g == g) return true;
+        return false;
+    }
+    // Evicts idle managed graphs, least recently used first, until `need` more bytes fit the
+    // budget or none is left; a graph whose handle is in use by the caller (lock held) is skipped.
+    void make_room(size_t need, const fastlbp_graph *keep) {
+        size_t cur = resident_bytes();
+        if (cur + need <= opts.memory_budget) return;
+        std::vector<fastlbp_graph *> idle;
+        for (auto *g : managed)
+            if (g != keep && graph_resident(g) && !is_active(g)) idle.push_back(g);
+        std::sort(idle.begin(), idle.end(),
+                  [](fastlbp_graph *a, fastlbp_graph *b) { return graph_last_use(a) < graph_last_use(b); });
+        for (auto *g : idle) {
+            if (cur + need <= opts.memory_budget) break;
+            std::unique_lock<std::recursive_mutex> lk(graph_mutex(g), std::try_to_lock);
+            if (!lk.owns_lock()) continue;
+            const size_t b = graph_state_bytes(g);
+            graph_evict(g);
+            cur -= b;
+            ++evictions;
+        }
+    }
 };
+
+namespace fastlbp {
+void server_forget(fastlbp_server *s, fastlbp_graph *g) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->managed.erase(g);
+    s->runs_of_graph.erase(g);
+}
+}  // namespace fastlbp
 
 void fastlbp_server::loop() {
     (void)hipSetDevice(opts.device);
@@ -88,10 +138,19 @@ void fastlbp_server::loop() {
                     ++it;
                     continue;
                 }
-                size_t need = graph_state_bytes(r->g);
-                if (!active.empty() && resident + need > opts.memory_budget) break;
+                // device memory: make room by evicting idle graphs, then restore this one
+                const size_t need = graph_resident(r->g) ? 0 : graph_state_bytes(r->g);
+                try {
+                    make_room(need, r->g);
+                } catch (DeviceError &) {
+                }
+                if (!active.empty() && resident_bytes() + need > opts.memory_budget) break;
                 it = pending.erase(it);
                 try {
+                    if (!graph_resident(r->g)) {
+                        graph_restore(r->g);
+                        ++restores;
+                    }
                     int rc = set_evidence(r->g, int32_t(r->ev_vars.size()), r->ev_vars.data(), r->ev_vals.data());
                     if (rc) {
                         r->status = rc;
@@ -113,9 +172,10 @@ void fastlbp_server::loop() {
                 }
                 r->warm = runs_of_graph[r->g] > 0;
                 r->t_start = Clock::now();
-                resident += need;
+                graph_last_use(r->g) = ++clock;
                 active.push_back(r);
             }
+            peak_resident = std::max(peak_resident, resident_bytes());
             gs.clear();
             damp.clear();
             for (auto &a : active) {
@@ -129,6 +189,7 @@ void fastlbp_server::loop() {
         std::vector<std::shared_ptr<Request>> finished;
         std::string err;
         float dev_ms = 0.f;
+        double launch_bytes = -1.0;
         try {
             // wide runs first (asynchronous, each on its own stream), then the persistent launch of
             // the narrow runs, which overlaps them
@@ -145,8 +206,16 @@ void fastlbp_server::loop() {
                 }
             }
             if (!narrow.empty()) {
+                std::vector<int32_t> it0(narrow.size());
+                for (size_t i = 0; i < narrow.size(); ++i) it0[i] = graph_host_state(narrow[i]).iter;
                 step_run(*launcher, int(narrow.size()), narrow.data(), narrow_damp.data(), opts.step_iters);
                 dev_ms = launcher_kernel_ms(launcher);
+                // method bytes of this persistent launch: each run's iterations in it
+                double bytes = 0.0;
+                for (size_t i = 0; i < narrow.size(); ++i)
+                    bytes += graph_method_bytes_per_iter(narrow[i], graph_host_state(narrow[i]).tol, narrow_damp[i]) *
+                             double(graph_host_state(narrow[i]).iter - it0[i]);
+                launch_bytes = bytes;
             }
             for (auto *g : wide) dev_ms = std::max(dev_ms, step_levels_finish(g));
             // the persistent launch refreshed the narrow runs' host state; the wide ones are read
@@ -165,6 +234,11 @@ void fastlbp_server::loop() {
         ++steps;
         busy_ms += step_ms;
         if (err.empty()) kernel_ms += dev_ms;
+        if (err.empty() && launch_bytes >= 0.0) {
+            ++persistent_launches;
+            persistent_ms += launcher_kernel_ms(launcher);
+            persistent_bytes += launch_bytes;
+        }
         for (auto it = active.begin(); it != active.end();) {
             auto r = *it;
             const RunState &hs = graph_host_state(r->g);
@@ -179,7 +253,7 @@ void fastlbp_server::loop() {
                 try {
                     r->p1.resize(graph_num_vars(r->g));
                     marginals_into(r->g, r->p1.data());
-                    fill_stats_public(r->g, r->stats, 0.f);
+                    fill_stats_public(r->g, r->stats, 0.f, r->damping);
                     r->status = 0;
                 } catch (DeviceError &e) {
                     r->status = FASTLBP_E_DEVICE;
@@ -187,13 +261,13 @@ void fastlbp_server::loop() {
                 }
             }
             r->t_done = Clock::now();
-            resident -= graph_state_bytes(r->g);
             runs_of_graph[r->g] += 1;
+            graph_last_use(r->g) = ++clock;
             if (r->status == 0) {
                 lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
                 ++completed;
                 updates += r->stats.message_updates;
-                alg_bytes += r->stats.algorithmic_bytes_per_iter * double(r->stats.iterations);
+                method_bytes += r->stats.method_bytes_per_iter * double(r->stats.iterations);
             }
             it = active.erase(it);
         }
@@ -283,6 +357,12 @@ int fastlbp_server_submit(fastlbp_server_t s, fastlbp_graph_t g, int32_t n_ev, c
             set_error("server is shutting down");
             return FASTLBP_E_STATE;
         }
+        if (graph_manager(g) && graph_manager(g) != s) {
+            set_error("graph is managed by another server");
+            return FASTLBP_E_STATE;
+        }
+        graph_set_manager(g, s);
+        s->managed.insert(g);
         r->ticket = s->next_ticket++;
         s->by_ticket[r->ticket] = r;
         s->pending.push_back(r);
@@ -351,7 +431,14 @@ int fastlbp_server_get_stats(fastlbp_server_t s, fastlbp_server_stats *out) {
     out->steps = s->steps;
     out->busy_ms = s->busy_ms;
     out->kernel_ms = s->kernel_ms;
-    out->algorithmic_bytes = s->alg_bytes;
+    out->method_bytes = s->method_bytes;
+    out->evictions = s->evictions;
+    out->restores = s->restores;
+    out->resident_bytes = s->resident_bytes();
+    out->peak_resident_bytes = s->peak_resident;
+    out->persistent_launches = s->persistent_launches;
+    out->persistent_ms = s->persistent_ms;
+    out->persistent_method_bytes = s->persistent_bytes;
     out->pending = int32_t(s->pending.size());
     out->active = int32_t(s->active.size());
     if (!s->lat_ms.empty()) {
@@ -381,6 +468,11 @@ void fastlbp_server_destroy(fastlbp_server_t s) {
     s->cv_work.notify_all();
     if (s->th.joinable()) s->th.join();
     s->cv_done.notify_all();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto *g : s->managed) graph_set_manager(g, nullptr);
+        s->managed.clear();
+    }
     launcher_destroy(s->launcher);
     delete s;
 }

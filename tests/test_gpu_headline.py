@@ -1,0 +1,139 @@
+"""The batched launch the throughput figure is measured on, checked directly: more than 256 FP32
+queries of the 200k-variable SmartFL-shaped graph (forward-backward schedule, 998 levels) in one
+continuous-batching server, 8 iterations per launch, undamped. With more than 256 runs the
+persistent executor takes its 512-thread float32 kernel, the one timed by the benchmark.
+
+Checks:
+* every query's marginals are bit-equal to the same query in a batch of a different composition
+  (order reversed, extra queries), and a sample of queries equals the query run alone (a server
+  with one active run, which takes the 1024-thread kernel);
+* one-step parity in the same launch shape: queries restarted from their own in-flight states
+  (set through fastlbp_messages_set) take one iteration, compared with one oracle iteration from
+  the same state (1e-5 absolute on messages, the FP32 one-step bound);
+* end to end at a fixed iteration count from uniform messages against the oracle (1e-4), for
+  queries the chaos guard finds insensitive; sensitive ones are covered by the one-step check.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_22337_amd as F
+from paper_2509_22337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_QUERIES = 272   # > 256: the 512-thread kernel
+STEP_ITERS = 8
+MAX_ITERS = 24    # three launches
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.load()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _evidence(w, q):
+    return w.evidence if q == 0 else W.smartfl_evidence(w, seed=1000 + q)
+
+
+def _clamps(ev):
+    v = np.flatnonzero(ev >= 0).astype(np.int32)
+    return v, ev[v].astype(np.int8)
+
+
+def _serve(handles, evs, max_active):
+    srv = F.Server(precision="fp32", max_active=max_active, step_iters=STEP_ITERS)
+    for h in handles:
+        h.messages_reset()
+        h.evidence_clear()
+    tickets = [srv.submit(h, *_clamps(ev), MAX_ITERS, TOL, 0.0) for h, ev in zip(handles, evs)]
+    out = [srv.wait(t) for t in tickets]
+    srv.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = W.smartfl(0)
+    evs = [_evidence(w, q) for q in range(N_QUERIES + 16)]
+    base = F.Graph.from_workload(w, precision="fp32", executor="persistent")
+    hs = [base] + [base.clone() for _ in range(N_QUERIES + 15)]
+    yield w, evs, hs
+    for h in hs:
+        h.close()
+
+
+def test_batched_launch_equals_other_batches_and_solo(c2):
+    w, evs, hs = c2
+    _say("C2 batched:", N_QUERIES, "queries, V", w.num_vars, "E", w.num_edges)
+    a = _serve(hs[:N_QUERIES], evs[:N_QUERIES], N_QUERIES)
+    # the same queries in another batch: reversed, with 16 other queries in front
+    order = list(range(N_QUERIES, N_QUERIES + 16)) + list(range(N_QUERIES - 1, -1, -1))
+    b = _serve([hs[i] for i in order], [evs[i] for i in order], len(order))
+    b = {q: r for q, r in zip(order, b)}
+    for q in range(N_QUERIES):
+        assert a[q][1]["iterations"] == b[q][1]["iterations"] == MAX_ITERS
+        assert np.array_equal(a[q][0], b[q][0]), f"query {q} differs between batches"
+    # alone: a server with one active run at a time
+    for q in range(0, N_QUERIES, N_QUERIES // 16):
+        (m1, s1, _), = _serve([hs[q]], [evs[q]], 1)
+        _say("solo", q, "max |batched - alone|", float(np.abs(m1 - a[q][0]).max()))
+        assert np.array_equal(m1, a[q][0]), f"query {q} differs from its run alone"
+        assert s1["iterations"] == a[q][1]["iterations"]
+
+
+def test_batched_launch_one_step_parity(c2):
+    w, evs, hs = c2
+    hs, evs = hs[:N_QUERIES], evs[:N_QUERIES]
+    _serve(hs, evs, N_QUERIES)  # in-flight states after 24 iterations
+    picks = list(range(3, N_QUERIES, N_QUERIES // 8))[:8]
+    start = {}
+    for q in picks:
+        p = hs[q].messages_get()
+        hs[q].messages_set(p)
+        start[q] = p
+    # one iteration of every query in one launch of the same shape
+    st = F.run_batch(hs, 1, 0.0, 0.0)
+    worst = 0.0
+    for q in picks:
+        assert st[q]["iterations"] == 1
+        p = start[q]
+        got = hs[q].messages_get()
+        _, _, om1, ost = oracle.bp_pairs(w, 1 - p, p, 1, 0.0, 0.0, ranks=w.edge_rank, evidence=evs[q])
+        err = float(np.abs(got - om1).max())
+        worst = max(worst, err)
+        _say("one step", q, "max |message - oracle|", err, "contradictions", st[q]["contradictions"],
+             ost["contradictions"])
+        assert err <= 1e-5
+        assert st[q]["contradictions"] == ost["contradictions"]
+    _say("one-step worst", worst)
+
+
+def test_batched_launch_end_to_end(c2):
+    w, evs, hs = c2
+    res = _serve(hs[:N_QUERIES], evs[:N_QUERIES], N_QUERIES)
+    checked = 0
+    rng = np.random.default_rng(0)
+    for q in range(8):
+        if checked == 2:
+            break
+        om, _, ost = oracle.bp(w, MAX_ITERS, TOL, 0.0, evidence=evs[q])
+        m1 = 0.5 + 1e-15 * rng.standard_normal(w.num_edges)
+        ob, _, _ = oracle.bp(w, MAX_ITERS, TOL, 0.0, evidence=evs[q], msg1=m1)
+        sensitive = float(np.abs(om - ob).max()) > 1e-10
+        err = float(np.abs(res[q][0] - om).max())
+        _say("end to end", q, "max |marginal - oracle|", err, "sensitive" if sensitive else "insensitive")
+        if not sensitive:
+            assert err <= 1e-4
+            checked += 1
+    assert checked >= 1
