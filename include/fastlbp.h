@@ -310,6 +310,25 @@ int fastlbp_evidence_clear(fastlbp_graph_t g);
  * damping lambda in [0,1). stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
 int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
 
+/* Size of the fixed device area fastlbp_run_noalloc works in, one per device, held from the first
+ * such call on a device until the process ends. */
+#define FASTLBP_NOALLOC_SCRATCH_BYTES 16384
+
+/* As fastlbp_run, for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the call allocates no device or host memory.
+ * The run's own state (iteration counters, convergence residual and contradiction partials) and
+ * the persistent executor's launch descriptor live in a fixed library area of
+ * FASTLBP_NOALLOC_SCRATCH_BYTES bytes per device, which one run always fits; the LEVELS and HYBRID
+ * executors launch their kernels directly instead of replaying a captured hipGraph (whose
+ * instantiation allocates). The handle's messages, beliefs and evidence are used and updated as
+ * by fastlbp_run, and the results are the same. Every call on a device shares that device's area
+ * and the area keeps the last call's contents (each call clears what it needs): calls that overlap
+ * on one device, from several threads or on several streams, race and must be serialised by the
+ * caller. Errors: E_INVALID_ARG, E_STATE (the handle's device state was evicted by a server:
+ * restoring it would allocate), E_DEVICE (the area's address could not be obtained, or a HIP call
+ * failed). */
+int fastlbp_run_noalloc(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
+
 /* Adaptive update strategies as rank generators (the randomized and residual-driven schedules of
  * related work, Section 6). The run proceeds in blocks of `every` iterations (the last block may be
  * shorter); before each block the generator gives every edge a rank, the dependency analysis splits

@@ -118,7 +118,7 @@ EXPORTS = [
     "fastlbp_server_create", "fastlbp_server_submit", "fastlbp_server_poll", "fastlbp_server_wait",
     "fastlbp_server_get_stats", "fastlbp_server_destroy", "fastlbp_alarm_loop", "fastlbp_autotune",
     "fastlbp_autotune_cache_get", "fastlbp_autotune_cache_put", "fastlbp_graph_get_info", "fastlbp_run_adaptive",
-    "fastlbp_ranks_random", "fastlbp_ranks_residual",
+    "fastlbp_ranks_random", "fastlbp_ranks_residual", "fastlbp_run_noalloc",
 ]
 
 _lib = None
@@ -158,6 +158,7 @@ def load() -> ctypes.CDLL:
     lib.fastlbp_evidence_set.argtypes = [P, i32, P, P]
     lib.fastlbp_evidence_clear.argtypes = [P]
     lib.fastlbp_run.argtypes = [P, i32, f64, f64, ctypes.POINTER(RunStats)]
+    lib.fastlbp_run_noalloc.argtypes = [P, i32, f64, f64, ctypes.POINTER(RunStats)]
     lib.fastlbp_marginals.argtypes = [P, P]
     lib.fastlbp_graph_get_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
     lib.fastlbp_run_adaptive.argtypes = [P, i32, i32, i32, ctypes.c_uint64, i32, f64, f64, ctypes.POINTER(RunStats)]
@@ -476,6 +477,12 @@ class Graph:
         st = RunStats()
         _check(load().fastlbp_run_adaptive(self._h, gen, int(groups), int(every), ctypes.c_uint64(int(seed) & (2**64 - 1)),
                                            int(max_iters), float(tol), float(damping), ctypes.byref(st)))
+        return st.as_dict()
+
+    def run_noalloc(self, max_iters: int, tol: float = 0.0, damping: float = 0.0) -> dict:
+        """fastlbp_run_noalloc: the same run without any allocation (fixed per-device scratch area)."""
+        st = RunStats()
+        _check(load().fastlbp_run_noalloc(self._h, int(max_iters), float(tol), float(damping), ctypes.byref(st)))
         return st.as_dict()
 
     def info(self) -> dict:

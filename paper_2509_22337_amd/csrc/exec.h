@@ -434,6 +434,18 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
         if (_e != hipSuccess) throw DeviceError{std::string(#x) + ": " + hipGetErrorString(_e)};           \
     } while (0)
 
+// Pinned host bytes per handle for staging one launch descriptor and one state header.
+constexpr size_t kFixedHostBytes = 2048;
+
+// Descriptor and state-header areas provided by the caller of a persistent launch (a device area
+// and a pinned host area of at least the launch's descriptor and header bytes).
+struct FixedArea {
+    void *dev;
+    size_t dev_bytes;
+    unsigned char *host;
+    size_t host_bytes;
+};
+
 // A set of device allocations freed together.
 struct DevPool {
     Alloc alloc;
@@ -606,6 +618,7 @@ struct fastlbp_graph {
     double *marg = nullptr;
     Launcher L;
     RunState *h_state = nullptr;  // pinned copy
+    unsigned char *h_fixed = nullptr;  // pinned staging of fastlbp_run_noalloc's launch descriptor
     void *ev_buf = nullptr;       // staging for evidence updates (indices + potentials)
     size_t ev_cap = 0;
     // captured iterations of the LEVELS executor
@@ -648,6 +661,7 @@ struct fastlbp_graph {
         state.release();
         alloc.put(ev_buf);
         if (h_state) (void)hipHostFree(h_state);
+        if (h_fixed) (void)hipHostFree(h_fixed);
     }
     template <class PP>
     DevGraph<typename PP::S, typename PP::V> view(double damping) const {
@@ -824,7 +838,9 @@ static void ensure_iteration_graph(fastlbp_graph *g, const DevGraph<typename PP:
 }
 
 template <class PP, bool ALL, bool DAMP>
-static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse) {
+// plain: launch every iteration's kernels directly instead of replaying a captured hipGraph (whose
+// instantiation allocates).
+static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse, bool plain) {
     auto dg = g->view<PP>(damping);
     hipStream_t s = g->L.stream;
     k_run_init<<<1, 64, 0, s>>>(g->st, max_iters, tol);
@@ -836,7 +852,7 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
     int per_iter_kernels = std::max(1, fuse ? g->P->hp.launches_hybrid : g->P->hp.launches_levels);
     int K = g->tune_graph_iters > 0 ? g->tune_graph_iters : std::max(1, std::min(32, 2048 / per_iter_kernels));
     K = std::min(K, max_iters);
-    bool use_graph = g->opts.use_graph != 0;
+    bool use_graph = g->opts.use_graph != 0 && !plain;
     if (use_graph) ensure_iteration_graph<PP, ALL, DAMP>(g, dg, K, damping, fuse);
     int done_iters = 0;
     while (true) {
@@ -857,8 +873,11 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
 // until it is done or its iteration count reaches its step_end (with step > 0, first set to
 // step iterations past the current count). On return every run's host state header is current.
 template <class PP>
+// fixed (optional): a caller-provided device area for the descriptors and state headers and a
+// pinned host area for their staging, used instead of the launcher's own buffers (which are
+// allocated on first use).
 static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping,
-                              int32_t step = 0) {
+                              int32_t step = 0, const FixedArea *fixed = nullptr) {
     if (n <= 0) return;
     bool teams = false, damp = false;
     for (int i = 0; i < n; ++i) {
@@ -868,10 +887,12 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
     const size_t dbytes = sizeof(RunDesc<PP>) * size_t(n);
     const size_t sbytes = kRunStateHeader * size_t(n);
     const size_t bytes = dbytes + sbytes;
-    void *d = lc.descs(bytes);
+    if (fixed && (bytes > fixed->dev_bytes || bytes > fixed->host_bytes))
+        throw DeviceError{"launch descriptors exceed the fixed area"};
+    void *d = fixed ? fixed->dev : lc.descs(bytes);
     int32_t *dstatus = (int32_t *)((unsigned char *)d + dbytes);
-    lc.hdesc.resize(dbytes);
-    RunDesc<PP> *h = (RunDesc<PP> *)lc.hdesc.data();
+    if (!fixed) lc.hdesc.resize(dbytes);
+    RunDesc<PP> *h = (RunDesc<PP> *)(fixed ? fixed->host : lc.hdesc.data());
     for (int i = 0; i < n; ++i) {
         h[i].g = gs[i]->view<PP>(damping[i]);
         h[i].g.prev = GPtr<typename PP::S>();  // the persistent level loop keeps its beliefs itself
@@ -880,7 +901,7 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
         h[i].status = GPtr<int32_t>(dstatus + i * int(kRunStateHeader / 4));
         h[i].step = step;
     }
-    unsigned char *hs = lc.status_host(sbytes);
+    unsigned char *hs = fixed ? fixed->host + dbytes : lc.status_host(sbytes);
     HIPCHK(hipMemcpyAsync(d, h, dbytes, hipMemcpyHostToDevice, lc.stream));
     const RunDesc<PP> *dd = (const RunDesc<PP> *)d;
     int nt = persistent_threads(gs[0]->precision(), teams, n);
@@ -966,12 +987,12 @@ static void step_levels_p(fastlbp_graph *g, double damping, int32_t iters) {
 
 // Runs of the LEVELS or HYBRID executor, dispatched over the plan's activity and damping.
 template <class PP>
-static void levels_run(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse) {
+static void levels_run(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse, bool plain) {
     bool all = g->P->hp.all_active != 0, damp = damping > 0.0;
-    if (all && damp) run_levels<PP, true, true>(g, max_iters, tol, damping, fuse);
-    if (all && !damp) run_levels<PP, true, false>(g, max_iters, tol, damping, fuse);
-    if (!all && damp) run_levels<PP, false, true>(g, max_iters, tol, damping, fuse);
-    if (!all && !damp) run_levels<PP, false, false>(g, max_iters, tol, damping, fuse);
+    if (all && damp) run_levels<PP, true, true>(g, max_iters, tol, damping, fuse, plain);
+    if (all && !damp) run_levels<PP, true, false>(g, max_iters, tol, damping, fuse, plain);
+    if (!all && damp) run_levels<PP, false, true>(g, max_iters, tol, damping, fuse, plain);
+    if (!all && !damp) run_levels<PP, false, false>(g, max_iters, tol, damping, fuse, plain);
 }
 
 // Plan of a schedule with known levels (runtime.hip), and one run on an executor.
@@ -980,13 +1001,15 @@ std::shared_ptr<Plan> plan_from_levels(const Structure &S, const Alloc &alloc, h
 void run_any(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec);
 
 // Instantiations, one translation unit per precision and executor (exec_*.hip).
-void levels_run_f32(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse);
-void levels_run_f64(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse);
+void levels_run_f32(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse, bool plain);
+void levels_run_f64(fastlbp_graph *g, int32_t max_iters, double tol, double damping, bool fuse, bool plain);
 void levels_step_f32(fastlbp_graph *g, double damping, int32_t iters);
 void levels_step_f64(fastlbp_graph *g, double damping, int32_t iters);
 void init_beliefs_f32(fastlbp_graph *g);
 void init_beliefs_f64(fastlbp_graph *g);
-void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
-void persistent_launch_f64(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
+void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
+                           const FixedArea *fixed = nullptr);
+void persistent_launch_f64(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
+                           const FixedArea *fixed = nullptr);
 
 }  // namespace fastlbp

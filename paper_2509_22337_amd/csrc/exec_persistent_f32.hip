@@ -3,8 +3,9 @@
 
 namespace fastlbp {
 
-void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
-    launch_persistent<PolLog32>(lc, n, gs, damping, step);
+void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
+                           const FixedArea *fixed) {
+    launch_persistent<PolLog32>(lc, n, gs, damping, step, fixed);
 }
 
 }  // namespace fastlbp

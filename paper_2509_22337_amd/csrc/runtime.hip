@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -278,15 +279,49 @@ __global__ void k_run_init_step(RunState *st, int32_t max_iters, double tol, int
     }
 }
 
+// Fixed device area of fastlbp_run_noalloc, one copy per device, held until the process ends:
+// the run state at offset 0, then the persistent executor's launch descriptor and state header.
+// Host code reaches it only through the address hipGetSymbolAddress returns for the device.
+constexpr size_t kScratchStateOffset = 0;
+constexpr size_t kScratchDescOffset = (sizeof(RunState) + 255) & ~size_t(255);
+constexpr size_t kScratchDescBytes = FASTLBP_NOALLOC_SCRATCH_BYTES - kScratchDescOffset;
+static_assert(kScratchDescBytes >= sizeof(RunDesc<PolLin64>) + kRunStateHeader &&
+                  kScratchDescBytes >= sizeof(RunDesc<PolLog32>) + kRunStateHeader,
+              "the scratch area holds one run state, one descriptor and one state header");
+static_assert(kFixedHostBytes >= sizeof(RunDesc<PolLin64>) + kRunStateHeader &&
+                  kFixedHostBytes >= sizeof(RunDesc<PolLog32>) + kRunStateHeader,
+              "the pinned staging holds one descriptor and one state header");
+static __device__ __align__(256) unsigned char scratch[FASTLBP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+static void *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) throw DeviceError{"device ordinal beyond the scratch table"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw DeviceError{std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        }
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
 // One run on the executor `exec` (the run state is reset first).
 void run_any(fastlbp_graph *g, int32_t max_iters, double tol, double damping, int exec) {
     const bool f32 = g->precision() == FASTLBP_FP32;
     if (exec == FASTLBP_EXEC_LEVELS || exec == FASTLBP_EXEC_HYBRID) {
         const bool fuse = exec == FASTLBP_EXEC_HYBRID;
         if (f32)
-            levels_run_f32(g, max_iters, tol, damping, fuse);
+            levels_run_f32(g, max_iters, tol, damping, fuse, false);
         else
-            levels_run_f64(g, max_iters, tol, damping, fuse);
+            levels_run_f64(g, max_iters, tol, damping, fuse, false);
         return;
     }
     k_run_init_step<<<1, 64, 0, g->L.stream>>>(g->st, max_iters, tol, max_iters);
@@ -493,6 +528,7 @@ static int finish_handle(fastlbp_graph *g) {
     HIPCHK(hipSetDevice(g->opts.device));
     g->L.init((hipStream_t)g->opts.stream, g->alloc);
     HIPCHK(hipHostMalloc((void **)&g->h_state, sizeof(RunState), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&g->h_fixed, kFixedHostBytes, hipHostMallocDefault));
     alloc_state(g);
     return FASTLBP_OK;
 }
@@ -558,6 +594,7 @@ int fastlbp_graph_create_terms(int32_t num_vars, int32_t num_factors, const int6
         g->P = make_plan(*S, g->alloc, s, FASTLBP_SCHED_FLOODING, nullptr, g->pparams);
         g->evidence.assign(hg.V, -1);
         HIPCHK(hipHostMalloc((void **)&g->h_state, sizeof(RunState), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g->h_fixed, kFixedHostBytes, hipHostMallocDefault));
         alloc_state(g.get());
     } catch (OomError &) {
         set_error("device allocation failed");
@@ -769,6 +806,69 @@ int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping
         set_error("device allocation failed");
         return FASTLBP_E_OOM;
     } catch (DeviceError &e) {
+        return device_error(e);
+    }
+    return FASTLBP_OK;
+}
+
+// Runs like fastlbp_run without allocating: the run state (iteration counters, residual and
+// contradiction partials) and the persistent executor's launch descriptor live in the device's
+// fixed scratch area, the descriptor is staged through the handle's pinned buffer allocated at
+// creation, and the LEVELS and HYBRID executors launch their kernels directly instead of replaying
+// a captured hipGraph. The handle's own run state is left untouched.
+int fastlbp_run_noalloc(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats) {
+    clear_error();
+    if (!g) {
+        set_error("graph is NULL");
+        return FASTLBP_E_INVALID_ARG;
+    }
+    int rc = check_run_args(max_iters, tol, damping);
+    if (rc) return rc;
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    if (!g->resident) {  // restoring would allocate
+        set_error("the handle's device state is evicted; any other call on it restores it");
+        return FASTLBP_E_STATE;
+    }
+    const int exec = choose_executor(g);
+    RunState *const own = g->st;
+    try {
+        HIPCHK(hipSetDevice(g->opts.device));
+        unsigned char *area = (unsigned char *)noalloc_scratch(g->opts.device);
+        hipStream_t s = g->L.stream;
+        HIPCHK(hipEventRecord(g->L.ev0, s));
+        g->st = (RunState *)(area + kScratchStateOffset);
+        const bool f32 = g->precision() == FASTLBP_FP32;
+        if (exec == FASTLBP_EXEC_LEVELS || exec == FASTLBP_EXEC_HYBRID) {
+            const bool fuse = exec == FASTLBP_EXEC_HYBRID;
+            if (f32)
+                levels_run_f32(g, max_iters, tol, damping, fuse, true);
+            else
+                levels_run_f64(g, max_iters, tol, damping, fuse, true);
+        } else {
+            k_run_init_step<<<1, 64, 0, s>>>(g->st, max_iters, tol, max_iters);
+            HIPCHK(hipGetLastError());
+            const FixedArea fa = {area + kScratchDescOffset, kScratchDescBytes, g->h_fixed, kFixedHostBytes};
+            fastlbp_graph *one[1] = {g};
+            if (f32)
+                persistent_launch_f32(g->L, 1, one, &damping, 0, &fa);
+            else
+                persistent_launch_f64(g->L, 1, one, &damping, 0, &fa);
+        }
+        HIPCHK(hipEventRecord(g->L.ev1, s));
+        HIPCHK(hipMemcpyAsync(g->h_state, g->st, kRunStateHeader, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        g->st = own;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g->L.ev0, g->L.ev1));
+        fastlbp_run_stats st;
+        fill_stats(g, exec, ms, damping, st);
+        if (stats) *stats = st;
+    } catch (OomError &) {
+        g->st = own;
+        set_error("allocation attempted by fastlbp_run_noalloc");
+        return FASTLBP_E_OOM;
+    } catch (DeviceError &e) {
+        g->st = own;
         return device_error(e);
     }
     return FASTLBP_OK;
