@@ -77,13 +77,13 @@ def query_evidence(w, q):
     return v, ev[v].astype(np.int8)
 
 
-def batched_steps(F, w, queries, steps, warmup, step_iters):
+def batched_steps(F, w, queries, steps, warmup, step_iters, keep=0):
     """Continuous-batching FP32 server, all queries of a step submitted at once."""
     import torch
     base = F.Graph.from_workload(w, precision="fp32", executor="persistent")
     handles = [base] + [base.clone() for _ in range(len(queries) - 1)]
     srv = F.Server(precision="fp32", max_active=len(queries), step_iters=step_iters)
-    lat, updates, iters, alg_bytes = [], 0, [], 0.0
+    lat, updates, iters, alg_bytes, kept = [], 0, [], 0.0, {}
     k0 = None
     for s in range(warmup + steps):
         if s == warmup:
@@ -95,6 +95,7 @@ def batched_steps(F, w, queries, steps, warmup, step_iters):
             h.evidence_clear()
         tickets = [srv.submit(h, v, x, w.max_iters, w.tol, w.damping) for h, (v, x) in zip(handles, queries)]
         res = [srv.wait(t) for t in tickets]
+        kept = {q: (res[q][0], res[q][1]) for q in range(min(keep, len(res)))}
         if s >= warmup:
             for _, st, l in res:
                 lat.append(l)
@@ -110,14 +111,14 @@ def batched_steps(F, w, queries, steps, warmup, step_iters):
         h.close()
     kernel_ms = st1["kernel_ms"] - st0["kernel_ms"]
     launches = st1["steps"] - st0["steps"]
-    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, alg_bytes=alg_bytes, kernel_ms=kernel_ms,
+    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, alg_bytes=alg_bytes, kept=kept, kernel_ms=kernel_ms,
                 launches=launches)
 
 
 def sequential_queries(F, w, queries, precision):
     import torch
     g = F.Graph.from_workload(w, precision=precision)
-    lat, updates, iters, dev_ms = [], 0, [], []
+    lat, updates, iters, dev_ms, margs, conv = [], 0, [], [], [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for v, x in queries:
@@ -126,7 +127,8 @@ def sequential_queries(F, w, queries, precision):
         g.evidence_clear()
         g.evidence_set(v, x)
         st = g.run(w.max_iters, w.tol, w.damping)
-        g.marginals()
+        margs.append(g.marginals())
+        conv.append(bool(st["converged"]))
         lat.append((time.perf_counter() - t0) * 1e3)
         updates += st["message_updates"]
         iters.append(st["iterations"])
@@ -134,7 +136,7 @@ def sequential_queries(F, w, queries, precision):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     g.close()
-    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, device_ms=dev_ms)
+    return dict(wall_s=wall, lat_ms=lat, updates=updates, iters=iters, device_ms=dev_ms, marginals=margs, converged=conv)
 
 
 def _replay_fp32(F, W, qs, hs, args, clamps):
@@ -652,7 +654,7 @@ def main():
     log(f"workload smartfl: V={w.num_vars} F={w.num_factors} E={w.num_edges} (non-prior {w.nonprior_edges()}), "
         f"{args.batch} queries per step")
 
-    rb = batched_steps(F, w, queries, args.steps, args.warmup, args.step_iters)
+    rb = batched_steps(F, w, queries, args.steps, args.warmup, args.step_iters, keep=args.fp64_queries)
     mups_b = rb["updates"] / rb["wall_s"]
     log(f"batched fp32: {rb['wall_s'] * 1e3 / args.steps:.1f} ms/step, {mups_b / 1e6:.1f} M updates/s")
     out = {
@@ -686,11 +688,13 @@ def main():
         traffic = T["bytes_per_launch"]
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                       "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-"
+                       "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-"
                                        "calibrated); null when the kernel sources or launch shape differ from "
                                        "the profiled ones", "kernel": "k_persistent<PolLog32>",
                        "launches": rb["launches"], "avg_launch_ms": round(rb["kernel_ms"] / max(1, rb["launches"]), 4),
-                       "algorithmic_bytes": rb["alg_bytes"]}
+                       "method_bytes_per_launch": rb["alg_bytes"] / max(1, rb["launches"]),
+                       "bytes_note": "method bytes: per touched factor edge 4 + 3s, per written edge 2s (tol > 0), "
+                                     "s = 4; each query's iterations; divided by the launches' device time"}
     if not args.batched_only:
         r64 = sequential_queries(F, w, queries[:args.fp64_queries], "fp64")
         mups64 = r64["updates"] / r64["wall_s"]
@@ -702,6 +706,12 @@ def main():
         out["solo_fp32"] = {"mups": round(r32["updates"] / r32["wall_s"], 1), "latency_ms": round(r32["lat_ms"][0], 3),
                             "iterations": r32["iters"][0], "device_ms": round(r32["device_ms"][0], 3)}
         out["batched_fp32_vs_plain_fp64"] = round(mups_b / mups64, 2)
+        errs = [float(np.abs(rb["kept"][q][0] - r64["marginals"][q]).max()) for q in range(len(r64["marginals"]))
+                if q in rb["kept"]]
+        conv = [e for q, e in enumerate(errs) if rb["kept"][q][1]["converged"] and r64["converged"][q]]
+        out["fp32_error"] = {"vs": "FP64 marginals of the same queries (plain FP64 runs)", "queries": len(errs),
+                             "max_abs": max(errs) if errs else None, "both_converged": len(conv),
+                             "max_abs_both_converged": max(conv) if conv else None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -305,9 +305,18 @@ int fastlbp_evidence_set(fastlbp_graph_t g, int32_t n, const int32_t *vars, cons
 /* Releases every clamp. */
 int fastlbp_evidence_clear(fastlbp_graph_t g);
 
-/* Runs belief propagation: at most max_iters iterations of the current schedule from the current
- * message state, stopping early when an iteration's residual is below tol (tol = 0: never).
- * damping lambda in [0,1). stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
+/* Runs belief propagation (Section 3.2, executed as in Section 4.3): at most max_iters iterations
+ * of the current schedule from the current message state. One iteration updates every non-PRIOR
+ * factor-to-variable message once: level by level in the order of the dependency analysis, each
+ * level computing the variable-to-factor messages of Eq.(1) its factors read and then their
+ * factor-to-variable messages of Eq.(2) in O(degree) per factor (Section 3.3). By Theorem 2 this
+ * gives exactly the messages of the update rule Eq.(5) under the schedule's preorder; FLOODING is
+ * the synchronous case, each message computed from the previous iteration's values. New messages
+ * are normalised and, with damping lambda in [0,1), mixed with the old ones as
+ * lambda * old + (1 - lambda) * new. The run stops after the first iteration whose residual (the
+ * largest change of P(x=1) over the messages it wrote) is below tol (tol = 0: never) or after
+ * max_iters iterations. Messages stay on the device: the next run starts from them (warm start).
+ * stats may be NULL. Errors: E_INVALID_ARG, E_DEVICE. */
 int fastlbp_run(fastlbp_graph_t g, int32_t max_iters, double tol, double damping, fastlbp_run_stats *stats);
 
 /* Size of the fixed device area fastlbp_run_noalloc works in, one per device, held from the first
@@ -372,14 +381,18 @@ int fastlbp_run_batch(int32_t n, fastlbp_graph_t *graphs, int32_t max_iters, dou
  * A variable whose incoming messages contradict (all products 0) gets 0.5. */
 int fastlbp_marginals(fastlbp_graph_t g, double *p1);
 
-/* Current factor-to-variable messages as P(x_v = 1) [E] (PRIOR edges report their prior). */
+/* Current factor-to-variable messages (the state Eq.(1)-(3) are computed from) as P(x_v = 1) [E]
+ * (PRIOR edges report their prior). For checkpointing a query's state, moving it to another
+ * handle, and checking one iteration against a reference from a known state. */
 int fastlbp_messages_get(fastlbp_graph_t g, double *f2v_p1);
 
-/* Sets the factor-to-variable messages from P(x_v = 1) [E] in [0,1] (PRIOR entries ignored).
- * Serves checkpoint/restore, warm start and one-step parity checks. Errors: E_INVALID_ARG. */
+/* Sets the factor-to-variable messages from P(x_v = 1) [E] in [0,1] (PRIOR entries ignored): the
+ * start state of the next run. For restoring a checkpoint, warm-starting from another handle's
+ * state, and one-step checks from a known state (exact 0 and 1 are represented exactly). Errors:
+ * E_INVALID_ARG. */
 int fastlbp_messages_set(fastlbp_graph_t g, const double *f2v_p1);
 
-/* Resets every message to uniform (cold start). */
+/* Resets every message to uniform, the initial state of a run (a cold start). */
 int fastlbp_messages_reset(fastlbp_graph_t g);
 
 /* ------------------------------------------------------------------------------------------ */
