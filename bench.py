@@ -252,6 +252,9 @@ def serving_mix(F, W, args):
     log(f"batched fp32: {len(res)} runs in {wall:.2f} s, {upd / wall / 1e9:.3f} G updates/s, "
         f"p50 {_lat(res)['p50_ms']} ms p99 {_lat(res)['p99_ms']} ms")
     n64 = min(args.fp64_graphs, len(qs))
+    if n64 == 0:  # profiling runs: the batched FP32 server only
+        return qs, res, dict(runs=len(res), wall_s=round(wall, 3), mups=round(upd / wall, 1), latency=dict(all=_lat(res)),
+                             server=sd, prefix=dict(latency={}), plain_fp64={}, fp32_error={})
     r64, wall64, upd64, busy64 = _fifo_fp64(F, qs, clamps, n64)
     log(f"plain fp64 FIFO on the first {n64} graphs: {len(r64)} runs in {wall64:.2f} s, "
         f"{upd64 / busy64 / 1e6:.1f} M updates/s busy, p50 {_lat(r64)['p50_ms']} ms p99 {_lat(r64)['p99_ms']} ms")
@@ -292,7 +295,19 @@ def flooding_runs(F, w, prec, steps, warmup, iters, label, tol=0.0):
     """`steps` timed cold runs of at most `iters` iterations on the LEVELS executor; the marginals of
     the last run are returned for the FP32-vs-FP64 comparison."""
     import torch
-    g = F.Graph.from_workload(w, precision=prec, executor="levels")
+    t0 = time.perf_counter()
+    kw = {}
+    if getattr(w, "term_off", None) is not None:
+        kw = dict(term_off=w.term_off, term_weight=w.term_weight, term_ind=w.term_ind)
+    g = F.Graph(w.num_vars, w.fac_off, w.edge_var, w.fac_type, w.fac_param, w.edge_param, precision=prec,
+                executor="levels", **kw)
+    log(f"{label} {prec}: graph created in {time.perf_counter() - t0:.1f} s")
+    if w.edge_rank is not None:
+        t0 = time.perf_counter()
+        g.schedule_set(F.SCHED_RANKED, w.edge_rank)
+        log(f"{label} {prec}: schedule set in {time.perf_counter() - t0:.1f} s")
+    if w.evidence is not None:
+        g.evidence_array(w.evidence)
     for s in range(warmup + steps):
         if s == warmup:
             torch.cuda.synchronize()

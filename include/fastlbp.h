@@ -444,6 +444,12 @@ typedef struct fastlbp_server_options {
                               graphs are evicted to host memory to stay within it, evicted graphs
                               are restored when admitted; 0 = 80% of the device's free memory at
                               creation */
+    int32_t step_levels;   /* > 0: a run advances per step by about this many levels (its iterations
+                              per step = step_levels / levels per iteration, at least 1; wide runs
+                              count kernel launches per iteration instead of levels), so a step costs
+                              about the same for every run and small graphs finish in a few steps
+                              instead of waiting out the steps of large ones; 0: every run advances
+                              by step_iters */
 } fastlbp_server_options;
 
 typedef struct fastlbp_server_stats {
@@ -466,7 +472,8 @@ typedef struct fastlbp_server_stats {
                                * iterations it advanced in the launch */
 } fastlbp_server_stats;
 
-/* Defaults: device 0, FP32, 256 active runs, 2 iterations per step, budget 0 (80% of free). */
+/* Defaults: device 0, FP32, 256 active runs, 2 iterations per step (used when step_levels is 0),
+ * budget 0 (80% of free), step_levels 4096. */
 void fastlbp_server_options_default(fastlbp_server_options *o);
 
 /* Starts a server with its own host thread and stream. Errors: E_INVALID_ARG, E_DEVICE. */

@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("step_iters", ctypes.c_int32), ("memory_budget", ctypes.c_size_t)]
+                ("step_iters", ctypes.c_int32), ("memory_budget", ctypes.c_size_t), ("step_levels", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -559,7 +559,8 @@ class Server:
     admitted between steps and advanced side by side, one workgroup per run."""
 
     def __init__(self, precision: str = "fp32", device: int = 0, max_active: int = 256, step_iters: int = 2,
-                 memory_budget: int = 0):
+                 memory_budget: int = 0, step_levels=None):
+        """step_levels: levels per step for each run (None: the library default, 0: step_iters)."""
         lib = load()
         o = ServerOptions()
         lib.fastlbp_server_options_default(ctypes.byref(o))
@@ -568,6 +569,8 @@ class Server:
         o.max_active = int(max_active)
         o.step_iters = int(step_iters)
         o.memory_budget = int(memory_budget)
+        if step_levels is not None:
+            o.step_levels = int(step_levels)
         h = ctypes.c_void_p()
         _check(lib.fastlbp_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

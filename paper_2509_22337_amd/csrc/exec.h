@@ -200,15 +200,15 @@ __host__ __device__ constexpr size_t stage_bytes(int32_t cap) {
 // phases. Thread tasks come as records whose loads are issued one phase ahead (the variable records
 // of a level while its factor phase runs, the factor records of the next level while the variable
 // phase runs), so each phase waits for one round of dependent loads. On entry `fr` / `pr` hold this
-// thread's first factor record of L0 and, if L0 is staged, its first staged variable record; on
-// exit they hold those of level `Lnext` (none when Lnext < 0). TEAMS adds the wavefront- and
+// thread's first factor record of L0 and, if L0 is staged, its first two staged variable records
+// (tid and tid + NT); on exit they hold those of level `Lnext` (none when Lnext < 0). TEAMS adds the wavefront- and
 // workgroup-per-factor paths and the weighted-term paths. foff / voff / staged give each level's
 // record offsets and staging flag.
 template <class P, bool DAMP, bool TEAMS, int NT, bool UNCOND, class FOff, class VOff, class Staged>
 __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
                                             int32_t L0, int32_t L1, int32_t Lnext, FOff foff, VOff voff,
                                             Staged staged, typename P::S *s_slot, Belief *b_slot,
-                                            TeamLds<typename P::V> *lds, Acc &acc, FacRec &fr, VarRecP &pr) {
+                                            TeamLds<typename P::V> *lds, Acc &acc, FacRec &fr, VarRecP (&pr)[2]) {
     using S = typename P::S;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         // variable phase input of an unstaged level, issued now (a staged level's variable phase
         // reads LDS only: its records were prefetched, its beliefs come from the factor phase)
         VarRec vr = {};
-        const VarRecP pc = pr;
+        const VarRecP pc0 = pr[0], pc1 = pr[1];
         if (v0 + tid < v1 && !stg) vr = vrec.ld_stream(v0 + tid);
         S *const slots = stg ? s_slot : nullptr;
         if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots, b_slot);
@@ -268,22 +268,25 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
                     const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
                     fr = frec.ld_stream(n0 + tid < n1 ? n0 + tid : 0);
                     const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                    pr = prec.ld_stream(staged(Ln) && m0 + tid < m1 ? m0 + tid : 0);
+                    pr[0] = prec.ld_stream(staged(Ln) && m0 + tid < m1 ? m0 + tid : 0);
+                    pr[1] = prec.ld_stream(staged(Ln) && m0 + tid + NT < m1 ? m0 + tid + NT : 0);
                 }
             } else {
                 fr = FacRec{};
-                pr = VarRecP{};
+                pr[0] = pr[1] = VarRecP{};
                 if (Ln >= 0) {
                     const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
                     if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
                     const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                    if (staged(Ln) && m0 + tid < m1) pr = prec.ld_stream(m0 + tid);
+                    if (staged(Ln) && m0 + tid < m1) pr[0] = prec.ld_stream(m0 + tid);
+                    if (staged(Ln) && m0 + tid + NT < m1) pr[1] = prec.ld_stream(m0 + tid + NT);
                 }
             }
         }
         if (stg) {
-            if (v0 + tid < v1) var_staged<P>(g, pc, s_slot, b_slot);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_staged<P>(g, prec.ld_stream(i), s_slot, b_slot);
+            if (v0 + tid < v1) var_staged<P>(g, pc0, s_slot, b_slot);
+            if (v0 + tid + NT < v1) var_staged<P>(g, pc1, s_slot, b_slot);
+            for (int32_t i = v0 + tid + 2 * NT; i < v1; i += NT) var_staged<P>(g, prec.ld_stream(i), s_slot, b_slot);
         } else {
             if (v0 + tid < v1) var_rec<P>(g, vr);
             for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
@@ -349,10 +352,11 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     __syncthreads();
     // records of level 0: the factor record, and the staged variable record when level 0 is staged
     FacRec fr = {};
-    VarRecP pr = {};
+    VarRecP pr[2] = {};
     if (NL > 0) {
         fr = frec.ld_stream(foff(0) + tid < foff(1) ? foff(0) + tid : 0);
-        pr = prec.ld_stream(staged(0) && voff(0) + tid < voff(1) ? voff(0) + tid : 0);
+        pr[0] = prec.ld_stream(staged(0) && voff(0) + tid < voff(1) ? voff(0) + tid : 0);
+        pr[1] = prec.ld_stream(staged(0) && voff(0) + tid + NT < voff(1) ? voff(0) + tid + NT : 0);
     }
     while (!s_done) {
         Acc acc = {0.0, 0u};
@@ -416,9 +420,10 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
     auto voff = [&](int32_t L) { return (int32_t)plan.vrec_off[L]; };
     auto staged = [&](int32_t L) { return staging && plan.level_lds[L] != 0; };
     FacRec fr = {};
-    VarRecP pr = {};
+    VarRecP pr[2] = {};
     if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld_stream(foff(L0) + tid);
-    if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr = plan.prec.ld_stream(voff(L0) + tid);
+    if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr[0] = plan.prec.ld_stream(voff(L0) + tid);
+    if (staged(L0) && voff(L0) + tid + NT < voff(L0 + 1)) pr[1] = plan.prec.ld_stream(voff(L0) + tid + NT);
     Acc acc = {0.0, 0u};
     level_range<P, DAMP, TEAMS, NT, false>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
     flush_acc<NT>(acc, st);
@@ -876,8 +881,9 @@ template <class PP>
 // fixed (optional): a caller-provided device area for the descriptors and state headers and a
 // pinned host area for their staging, used instead of the launcher's own buffers (which are
 // allocated on first use).
+// steps (optional): each run's own step, replacing `step`.
 static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping,
-                              int32_t step = 0, const FixedArea *fixed = nullptr) {
+                              int32_t step = 0, const FixedArea *fixed = nullptr, const int32_t *steps = nullptr) {
     if (n <= 0) return;
     bool teams = false, damp = false;
     for (int i = 0; i < n; ++i) {
@@ -899,7 +905,7 @@ static void launch_persistent(Launcher &lc, int n, fastlbp_graph *const *gs, con
         h[i].plan = gs[i]->P->view();
         h[i].st = GPtr<RunState>(gs[i]->st);
         h[i].status = GPtr<int32_t>(dstatus + i * int(kRunStateHeader / 4));
-        h[i].step = step;
+        h[i].step = steps ? steps[i] : step;
     }
     unsigned char *hs = fixed ? fixed->host + dbytes : lc.status_host(sbytes);
     HIPCHK(hipMemcpyAsync(d, h, dbytes, hipMemcpyHostToDevice, lc.stream));
@@ -1008,8 +1014,8 @@ void levels_step_f64(fastlbp_graph *g, double damping, int32_t iters);
 void init_beliefs_f32(fastlbp_graph *g);
 void init_beliefs_f64(fastlbp_graph *g);
 void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
-                           const FixedArea *fixed = nullptr);
+                           const FixedArea *fixed = nullptr, const int32_t *steps = nullptr);
 void persistent_launch_f64(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
-                           const FixedArea *fixed = nullptr);
+                           const FixedArea *fixed = nullptr, const int32_t *steps = nullptr);
 
 }  // namespace fastlbp

@@ -4,8 +4,8 @@
 namespace fastlbp {
 
 void persistent_launch_f32(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step,
-                           const FixedArea *fixed) {
-    launch_persistent<PolLog32>(lc, n, gs, damping, step, fixed);
+                           const FixedArea *fixed, const int32_t *steps) {
+    launch_persistent<PolLog32>(lc, n, gs, damping, step, fixed, steps);
 }
 
 }  // namespace fastlbp

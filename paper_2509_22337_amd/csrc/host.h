@@ -87,7 +87,7 @@ struct HostPlan {
     // task records of the weighted-term thread bucket (12 int32 each, TermRec), per level
     std::vector<int32_t> trec, trec_off;
     // levels whose new messages the persistent executor stages in LDS: flag per level, variable
-    // tasks with staging slots (8 int32 each, in vrec's order), most slots of a staged level
+    // tasks with staging slots (4 int32 each, in vrec's order), most slots of a staged level
     std::vector<int32_t> level_lds;
     std::vector<int32_t> prec;
     int32_t stage_slots = 0;

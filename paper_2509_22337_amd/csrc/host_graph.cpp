@@ -441,6 +441,28 @@ void HostGraph::set_terms(const int64_t *toff, const double *tw, const int8_t *t
     }
 }
 
+namespace {
+
+// Stable reordering of v by an integer key in [0, nkeys): a counting sort.
+template <class K>
+void counting_sort(std::vector<int32_t> &v, int64_t nkeys, K key, std::vector<int32_t> &tmp) {
+    std::vector<int64_t> cnt(size_t(nkeys) + 1, 0);
+    for (int32_t x : v) cnt[size_t(key(x)) + 1]++;
+    for (int64_t k = 0; k < nkeys; ++k) cnt[size_t(k) + 1] += cnt[size_t(k)];
+    tmp.resize(v.size());
+    for (int32_t x : v) tmp[size_t(cnt[size_t(key(x))]++)] = x;
+    v.swap(tmp);
+}
+
+// Stable reordering of v by a non-negative 32-bit key: two 16-bit counting passes.
+template <class K>
+void radix_sort32(std::vector<int32_t> &v, K key, std::vector<int32_t> &tmp) {
+    counting_sort(v, 1 << 16, [&](int32_t x) { return int64_t(uint32_t(key(x)) & 0xffffu); }, tmp);
+    counting_sort(v, 1 << 16, [&](int32_t x) { return int64_t(uint32_t(key(x)) >> 16); }, tmp);
+}
+
+}  // namespace
+
 int factor_bucket(int deg, const PlanParams &pp) {
     if (deg <= pp.thread_max_deg) return FB_THREAD;
     if (deg <= pp.wave_max_deg) return FB_WAVE;
@@ -474,6 +496,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     bytes_per_iter = 0.0;
     updates_per_iter = 0;
     touched_edges_per_iter = noisy_params_per_iter = term_weights_per_iter = term_entries_per_iter = 0;
+    std::vector<int32_t> lv;
     for (int32_t a = 0; a < g.F; ++a) {
         if (g.fac_type[a] == FASTLBP_PRIOR) continue;
         int64_t b = g.fac_off[a], d = g.fac_off[a + 1] - b;
@@ -481,7 +504,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         int bucket = terms ? (d <= kThreadMaxDeg ? FB_TERMS_THREAD : FB_TERMS_WAVE) : factor_bucket(int(d), pp);
         int32_t prev = -1;
         // levels of a factor's edges in ascending order of level, each level once
-        std::vector<int32_t> lv;
+        lv.clear();
         for (int64_t e = b; e < b + d; ++e) lv.push_back(edge_exec_level[e]);
         std::sort(lv.begin(), lv.end());
         for (int32_t L : lv) {
@@ -507,38 +530,41 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             }
         }
     }
-    // variables whose incoming messages a level writes: their beliefs are refreshed after it
-    for (int64_t e = 0; e < g.E; ++e) {
-        int32_t L = edge_exec_level[e];
-        if (L < 0) continue;
-        ++updates_per_iter;
-        bytes_per_iter += msg_bytes;  // written message
-        int32_t v = g.edge_var[e];
-        int vb = g.var_deg[v] <= pp.var_thread_max_deg ? VB_THREAD : VB_WAVE;
-        var_by_level[L * VB_COUNT + vb].push_back(v);
-    }
-    for (auto &lst : var_by_level) {
-        std::sort(lst.begin(), lst.end());
-        lst.erase(std::unique(lst.begin(), lst.end()), lst.end());
-        // list entry, offsets, phi, belief write; per edge: edge id and message
-        for (int32_t v : lst) bytes_per_iter += 4 + 8 + 2 * sizeof(Belief) + double(g.var_deg[v]) * (4 + msg_bytes);
+    // variables whose incoming messages a level writes: their beliefs are refreshed after it. Built
+    // from the variable-major rows, so every level's list comes out sorted and without repeats.
+    for (int64_t e = 0; e < g.E; ++e)
+        if (edge_exec_level[e] >= 0) {
+            ++updates_per_iter;
+            bytes_per_iter += msg_bytes;  // written message
+        }
+    for (int32_t v = 0; v < g.V; ++v) {
+        lv.clear();
+        for (int32_t q = g.var_off[v]; q < g.var_off[v + 1]; ++q) lv.push_back(edge_exec_level[g.var_edge[q]]);
+        std::sort(lv.begin(), lv.end());
+        const int vb = g.var_deg[v] <= pp.var_thread_max_deg ? VB_THREAD : VB_WAVE;
+        for (size_t i = 0; i < lv.size(); ++i) {
+            if (lv[i] < 0 || (i > 0 && lv[i] == lv[i - 1])) continue;
+            var_by_level[size_t(lv[i]) * VB_COUNT + vb].push_back(v);
+            // list entry, offsets, phi, belief write; per edge: edge id and message
+            bytes_per_iter += 4 + 8 + 2 * sizeof(Belief) + double(g.var_deg[v]) * (4 + msg_bytes);
+        }
     }
     auto fdeg = [&](int32_t a) { return int32_t(g.fac_off[a + 1] - g.fac_off[a]); };
+    std::vector<int32_t> sort_tmp;
     for (int b = 0; b < FB_COUNT; ++b) {
         fac_list[b].clear();
         fac_lvl_off[b].assign(1, 0);
         for (int32_t L = 0; L < exec_levels; ++L) {
             auto &src = fac_by_level[L * FB_COUNT + b];
-            // thread bucket: by degree, then type (a wavefront follows one code path); wider
-            // buckets: largest first, so the longest tasks start early
-            if (b == FB_THREAD)
-                std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
-                    int dx = fdeg(x), dy = fdeg(y);
-                    if (dx != dy) return dx < dy;
-                    if (g.fac_type[x] != g.fac_type[y]) return g.fac_type[x] < g.fac_type[y];
-                    return x < y;
-                });
-            else if (b == FB_TERMS_THREAD)  // by degree, then term count: a wavefront's loops agree
+            // thread bucket: by degree, then type (a wavefront follows one code path), then first
+            // variable (neighbouring threads gather neighbouring beliefs); wider buckets: largest
+            // first, so the longest tasks start early
+            // (lists are built in factor order, and the sorts below are stable)
+            if (b == FB_THREAD) {
+                radix_sort32(src, [&](int32_t x) { return g.edge_var[g.fac_off[x]]; }, sort_tmp);
+                counting_sort(src, int64_t(kThreadMaxDeg + 1) * 8,
+                              [&](int32_t x) { return int64_t(fdeg(x)) * 8 + g.fac_type[x]; }, sort_tmp);
+            } else if (b == FB_TERMS_THREAD)  // by degree, then term count: a wavefront's loops agree
                 std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
                     int dx = fdeg(x), dy = fdeg(y);
                     if (dx != dy) return dx < dy;
@@ -546,10 +572,8 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                     return lx != ly ? lx < ly : x < y;
                 });
             else
-                std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
-                    int dx = fdeg(x), dy = fdeg(y);
-                    return dx != dy ? dx > dy : x < y;
-                });
+                counting_sort(src, kBlockMaxDeg + 1, [&](int32_t x) { return int64_t(kBlockMaxDeg - std::min(fdeg(x), kBlockMaxDeg)); },
+                              sort_tmp);
             fac_list[b].insert(fac_list[b].end(), src.begin(), src.end());
             fac_lvl_off[b].push_back(int32_t(fac_list[b].size()));
         }
@@ -560,8 +584,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         var_lvl_off[b].assign(1, 0);
         for (int32_t L = 0; L < exec_levels; ++L) {
             auto &src = var_by_level[L * VB_COUNT + b];
-            if (b == VB_THREAD)
-                std::stable_sort(src.begin(), src.end(), [&](int32_t x, int32_t y) { return vkey(x) < vkey(y); });
+            if (b == VB_THREAD) counting_sort(src, kVarRecEdges + 1, vkey, sort_tmp);
             var_list[b].insert(var_list[b].end(), src.begin(), src.end());
             var_lvl_off[b].push_back(int32_t(var_list[b].size()));
         }
@@ -572,6 +595,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     // e0..e4}. A degree group is padded to a multiple of 64 with copies of its first record that
     // write nothing (factor: no active edge; variable: padding flag).
     frec.clear();
+    frec.reserve(size_t(fac_lvl_off[FB_THREAD].back() + 64 * std::max(exec_levels, 1) * 8) * 12);
     frec_off.assign(1, 0);
     for (int32_t L = 0; L < exec_levels; ++L) {
         const int32_t i0 = fac_lvl_off[FB_THREAD][L], i1 = fac_lvl_off[FB_THREAD][L + 1];
@@ -592,16 +616,16 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                 frec.insert(frec.end(), r, r + 12);
             }
             const size_t first = frec.size() - size_t(j - i) * 12;
-            while ((frec.size() / 12) % 64) {
-                std::vector<int32_t> r(frec.begin() + first, frec.begin() + first + 12);
-                r[1] &= 0xffff;  // no active edge
-                frec.insert(frec.end(), r.begin(), r.end());
-            }
+            int32_t pad[12];
+            std::copy(frec.begin() + first, frec.begin() + first + 12, pad);
+            pad[1] &= 0xffff;  // no active edge
+            while ((frec.size() / 12) % 64) frec.insert(frec.end(), pad, pad + 12);
             i = j;
         }
         frec_off.push_back(int32_t(frec.size() / 12));
     }
     vrec.clear();
+    vrec.reserve(size_t(var_lvl_off[VB_THREAD].back() + 64 * std::max(exec_levels, 1) * 6) * 8);
     vrec_off.assign(1, 0);
     for (int32_t L = 0; L < exec_levels; ++L) {
         const int32_t i0 = var_lvl_off[VB_THREAD][L], i1 = var_lvl_off[VB_THREAD][L + 1];
@@ -618,11 +642,10 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                 vrec.insert(vrec.end(), r, r + 8);
             }
             const size_t first = vrec.size() - size_t(j - i) * 8;
-            while ((vrec.size() / 8) % 64) {
-                std::vector<int32_t> r(vrec.begin() + first, vrec.begin() + first + 8);
-                r[2] |= 1 << 30;  // padding: computes, stores nothing
-                vrec.insert(vrec.end(), r.begin(), r.end());
-            }
+            int32_t pad[8];
+            std::copy(vrec.begin() + first, vrec.begin() + first + 8, pad);
+            pad[2] |= 1 << 30;  // padding: computes, stores nothing
+            while ((vrec.size() / 8) % 64) vrec.insert(vrec.end(), pad, pad + 8);
             i = j;
         }
         vrec_off.push_back(int32_t(vrec.size() / 8));
@@ -647,42 +670,47 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         trec_off.push_back(int32_t(trec.size() / 12));
     }
     // incremental variable phase (LEVELS executor): which (level, variable) tasks write only part
-    // of the variable's edges; the written edges of every level grouped by variable
-    {
+    // of the variable's edges; the written edges of every level grouped by variable, in variable
+    // order (filled from the variable-major rows, so no sort is needed). Flooding writes every edge
+    // of every variable in its one level: nothing to do there.
+    drec.clear();
+    dedge.clear();
+    dwave.clear();
+    drec_off.assign(1, 0);
+    dwave_off.assign(1, 0);
+    has_delta = 0;
+    if (!flooding) {
         std::vector<int64_t> lcnt(size_t(exec_levels) + 1, 0);
         for (int64_t e = 0; e < g.E; ++e)
             if (edge_exec_level[e] >= 0) lcnt[size_t(edge_exec_level[e]) + 1]++;
         for (int32_t L = 0; L < exec_levels; ++L) lcnt[size_t(L) + 1] += lcnt[size_t(L)];
         std::vector<int64_t> pos(lcnt.begin(), lcnt.end() - 1);
         std::vector<int32_t> by_level(static_cast<size_t>(lcnt[size_t(exec_levels)]));
-        for (int64_t e = 0; e < g.E; ++e)
-            if (edge_exec_level[e] >= 0) by_level[size_t(pos[size_t(edge_exec_level[e])]++)] = int32_t(e);
-        has_delta = 0;
+        for (int32_t v = 0; v < g.V; ++v)
+            for (int32_t q = g.var_off[v]; q < g.var_off[v + 1]; ++q) {
+                const int32_t e = g.var_edge[q];
+                const int32_t L = edge_exec_level[e];
+                if (L >= 0) by_level[size_t(pos[size_t(L)]++)] = e;
+            }
         for (int32_t L = 0; L < exec_levels && !has_delta; ++L) {
-            auto b = by_level.begin() + lcnt[size_t(L)], en = by_level.begin() + lcnt[size_t(L) + 1];
-            std::stable_sort(b, en, [&](int32_t x, int32_t y) { return g.edge_var[x] < g.edge_var[y]; });
-            for (auto it = b; it != en;) {
-                auto jt = it;
-                while (jt != en && g.edge_var[*jt] == g.edge_var[*it]) ++jt;
-                if (int32_t(jt - it) < g.var_deg[g.edge_var[*it]]) has_delta = 1;
-                it = jt;
+            const int64_t b = lcnt[size_t(L)], en = lcnt[size_t(L) + 1];
+            for (int64_t i = b; i < en && !has_delta;) {
+                int64_t j = i;
+                while (j < en && g.edge_var[by_level[size_t(j)]] == g.edge_var[by_level[size_t(i)]]) ++j;
+                if (int32_t(j - i) < g.var_deg[g.edge_var[by_level[size_t(i)]]]) has_delta = 1;
+                i = j;
             }
         }
-        drec.clear();
-        dedge.clear();
-        dwave.clear();
-        drec_off.assign(1, 0);
-        dwave_off.assign(1, 0);
+        std::vector<std::array<int32_t, 8>> recs;
         for (int32_t L = 0; has_delta && L < exec_levels; ++L) {
-            auto b = by_level.begin() + lcnt[size_t(L)], en = by_level.begin() + lcnt[size_t(L) + 1];
-            std::stable_sort(b, en, [&](int32_t x, int32_t y) { return g.edge_var[x] < g.edge_var[y]; });
+            const int64_t b = lcnt[size_t(L)], en = lcnt[size_t(L) + 1];
             // records of the level, then sorted by (kind, edges held) so a wavefront runs one shape
-            std::vector<std::array<int32_t, 8>> recs;
-            for (auto it = b; it != en;) {
-                auto jt = it;
-                const int32_t v = g.edge_var[*it];
-                while (jt != en && g.edge_var[*jt] == v) ++jt;
-                const int32_t w = int32_t(jt - it), deg = g.var_deg[v];
+            recs.clear();
+            for (int64_t i = b; i < en;) {
+                const int32_t v = g.edge_var[by_level[size_t(i)]];
+                int64_t j = i;
+                while (j < en && g.edge_var[by_level[size_t(j)]] == v) ++j;
+                const int32_t w = int32_t(j - i), deg = g.var_deg[v];
                 std::array<int32_t, 8> r{};
                 r[0] = v;
                 if (w == deg && deg <= pp.var_thread_max_deg) {  // rebuild from the row
@@ -694,33 +722,39 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                     r[1] = int32_t(dedge.size());
                     r[2] = w | (1 << 29);
                     for (int q = 0; q < w; ++q) {
-                        if (q < kVarRecEdges) r[3 + q] = *(it + q);
-                        dedge.push_back(*(it + q));
+                        if (q < kVarRecEdges) r[3 + q] = by_level[size_t(i + q)];
+                        dedge.push_back(by_level[size_t(i + q)]);
                     }
                     recs.push_back(r);
                 } else {
                     dwave.push_back(v);  // many written edges of a high-degree variable: rebuild by wavefront
                 }
-                it = jt;
+                i = j;
             }
             auto key = [](const std::array<int32_t, 8> &r) {
                 return ((r[2] >> 29) & 1) * 16 + std::min<int32_t>(r[2] & 0xffff, kVarRecEdges);
             };
-            std::stable_sort(recs.begin(), recs.end(),
-                             [&](const std::array<int32_t, 8> &x, const std::array<int32_t, 8> &y) { return key(x) < key(y); });
+            {  // stable by key (32 kinds)
+                std::vector<std::array<int32_t, 8>> byk[32];
+                for (auto &r : recs) byk[key(r)].push_back(r);
+                recs.clear();
+                for (auto &bk : byk) recs.insert(recs.end(), bk.begin(), bk.end());
+            }
             for (size_t i = 0; i < recs.size();) {
                 size_t j = i;
                 while (j < recs.size() && key(recs[j]) == key(recs[i])) ++j;
                 for (size_t k = i; k < j; ++k) drec.insert(drec.end(), recs[k].begin(), recs[k].end());
-                for (size_t k = j - i; k % 64; ++k) {  // padding copies of the group's first record
-                    std::array<int32_t, 8> p = recs[i];
-                    p[2] |= 1 << 30;
-                    drec.insert(drec.end(), p.begin(), p.end());
-                }
+                std::array<int32_t, 8> p = recs[i];  // padding copies of the group's first record
+                p[2] |= 1 << 30;
+                for (size_t k = j - i; k % 64; ++k) drec.insert(drec.end(), p.begin(), p.end());
                 i = j;
             }
             drec_off.push_back(int32_t(drec.size() / 8));
             dwave_off.push_back(int32_t(dwave.size()));
+        }
+        if (!has_delta) {
+            drec_off.assign(1, 0);
+            dwave_off.assign(1, 0);
         }
     }
     // staging in LDS: a level qualifies when all of its written edges come from thread-bucket
@@ -734,7 +768,7 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
     bool any_narrow = false;
     for (int32_t L = 0; L < exec_levels && !any_narrow; ++L)
         any_narrow = frec_off[L + 1] - frec_off[L] <= kMaxStageSlots;
-    if (any_narrow) prec.assign(vrec.size(), 0);
+    if (any_narrow) prec.assign(vrec.size() / 8 * 4, 0);
     std::vector<int32_t> edge_slot(any_narrow ? g.E : 0, -1);
     for (int32_t L = 0; any_narrow && L < exec_levels; ++L) {
         bool ok = fac_lvl_off[FB_WAVE][L + 1] == fac_lvl_off[FB_WAVE][L] &&
@@ -755,9 +789,9 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         for (int32_t i = vrec_off[L]; ok && i < vrec_off[L + 1]; ++i) {
             const int32_t *r = &vrec[size_t(i) * 8];
             const int32_t v = r[0];
-            int32_t *q = &prec[size_t(i) * 8];
+            int32_t *q = &prec[size_t(i) * 4];
             q[0] = v;
-            int32_t n = 0;
+            int32_t n = 0, sl[kStagedEdges] = {0, 0, 0, 0, 0, 0};
             for (int32_t p = g.var_off[v]; p < g.var_off[v + 1]; ++p) {
                 const int32_t e = g.var_edge[p];
                 if (edge_exec_level[e] != L) continue;
@@ -765,10 +799,13 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
                     ok = false;
                     break;
                 }
-                q[2 + n++] = edge_slot[e];
+                sl[n++] = edge_slot[e];
             }
             if (n == 0) ok = false;  // a staged task reads its belief from its first slot
-            q[1] = n | (r[2] & (1 << 30));  // keeps the padding flag
+            const uint32_t pad = (r[2] >> 30) & 1;  // keeps the padding flag
+            q[1] = int32_t(uint32_t(n) | pad << 3 | uint32_t(sl[0]) << 4 | uint32_t(sl[1]) << 18);
+            q[2] = int32_t(uint32_t(sl[2]) | uint32_t(sl[3]) << 16);
+            q[3] = int32_t(uint32_t(sl[4]) | uint32_t(sl[5]) << 16);
         }
         level_lds[L] = ok ? 1 : 0;
         if (ok) stage_slots = std::max(stage_slots, slots);

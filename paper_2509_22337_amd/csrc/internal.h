@@ -55,7 +55,11 @@ void launcher_destroy(Launcher *l);
 hipStream_t launcher_stream(Launcher *l);
 float launcher_kernel_ms(Launcher *l);  // duration of the last persistent launch (HIP events)
 void step_begin(fastlbp_graph *g, int32_t max_iters, double tol, int32_t step);
-void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step);
+void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, const int32_t *steps);
+// Levels one iteration of the handle's schedule executes, and kernel launches of one iteration on
+// the LEVELS executor (the server sizes each run's step by them).
+int32_t graph_exec_levels(fastlbp_graph *g);
+int32_t graph_launches_per_iter(fastlbp_graph *g);
 void read_state(fastlbp_graph *g, hipStream_t s);
 // Runs whose levels are too wide for one workgroup (the LEVELS executor) are stepped on their own
 // stream instead: step_levels_enqueue queues `iters` iterations without waiting, step_levels_finish

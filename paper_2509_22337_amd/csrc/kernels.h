@@ -927,16 +927,16 @@ __device__ __forceinline__ void var_delta(const DevGraph<typename P::S, typename
 template <class P>
 __device__ __forceinline__ void var_staged(const DevGraph<typename P::S, typename P::V> &g, const VarRecP &r,
                                            const typename P::S *slots, const Belief *bslots) {
-    const int n = r.n & 0xffff;
-    const bool pad = (r.n >> 30) & 1;
-    Belief B = bslots[r.s[0]];
+    const int n = r.n();
+    Belief B = bslots[r.slot(0)];
 #pragma unroll
     for (int j = 0; j < kStagedEdges; ++j)
         if (j < n) {
-            belief_sub<P>(B, slots[2 * r.s[j] + 1]);
-            belief_add<P>(B, slots[2 * r.s[j]]);
+            const int32_t s = r.slot(j);
+            belief_sub<P>(B, slots[2 * s + 1]);
+            belief_add<P>(B, slots[2 * s]);
         }
-    if (!pad) g.bel.st(r.v, B);
+    if (!r.pad()) g.bel.st(r.v, B);
 }
 
 // ------------------------------------------------------------------------------------------------

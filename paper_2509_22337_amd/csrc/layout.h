@@ -173,15 +173,22 @@ struct alignas(16) VarRec {
     int32_t e[5];           // its first edges (the rest from var_edge)
 };
 
-// Variable task of a level staged in LDS (persistent executor): the variable, how many of its
-// messages the level writes (| padding record << 30) and their staging slots. Its belief is
-// updated from the value before the level plus (new - old) of those messages.
+// Variable task of a level staged in LDS (persistent executor), 16 bytes so that two fit the
+// registers of one prefetch: the variable, how many of its messages the level writes, a padding
+// flag and their staging slots (n | pad << 3 | s0 << 4 | s1 << 18, then s2 | s3 << 16 and
+// s4 | s5 << 16). Its belief is updated from the value before the level plus (new - old) of those
+// messages.
 constexpr int kStagedEdges = 6;
-constexpr int kMaxStageSlots = 2048;  // written edges of a level that may be staged in LDS
+constexpr int kMaxStageSlots = 2048;  // written edges of a level that may be staged in LDS (< 2^14)
 struct alignas(16) VarRecP {
     int32_t v;
-    int32_t n;
-    int32_t s[kStagedEdges];
+    uint32_t a, b, c;
+    __host__ __device__ int n() const { return int(a & 7u); }
+    __host__ __device__ bool pad() const { return ((a >> 3) & 1u) != 0; }
+    __host__ __device__ int32_t slot(int j) const {
+        const uint32_t w = j < 2 ? (a >> (4 + 14 * j)) & 0x3fffu : ((j < 4 ? b : c) >> (16 * (j & 1))) & 0xffffu;
+        return int32_t(w);
+    }
 };
 
 struct DevPlan {

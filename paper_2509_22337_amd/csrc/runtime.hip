@@ -375,11 +375,16 @@ double graph_method_bytes_per_iter(fastlbp_graph *g, double tol, double damping)
     return g->P->hp.method_bytes_per_iter(int(g->S->msg_bytes()), tol > 0.0 || damping > 0.0);
 }
 
-void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, int32_t step) {
+void step_run(Launcher &lc, int n, fastlbp_graph *const *gs, const double *damping, const int32_t *steps) {
     if (gs[0]->precision() == FASTLBP_FP32)
-        persistent_launch_f32(lc, n, gs, damping, step);
+        persistent_launch_f32(lc, n, gs, damping, 0, nullptr, steps);
     else
-        persistent_launch_f64(lc, n, gs, damping, step);
+        persistent_launch_f64(lc, n, gs, damping, 0, nullptr, steps);
+}
+
+int32_t graph_exec_levels(fastlbp_graph *g) { return g->P->hp.exec_levels; }
+int32_t graph_launches_per_iter(fastlbp_graph *g) {
+    return choose_executor(g) == FASTLBP_EXEC_HYBRID ? g->P->hp.launches_hybrid : g->P->hp.launches_levels;
 }
 
 bool graph_wide(fastlbp_graph *g) { return choose_executor(g) != FASTLBP_EXEC_PERSISTENT; }

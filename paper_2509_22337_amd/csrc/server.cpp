@@ -36,6 +36,9 @@
 using namespace fastlbp;
 using Clock = std::chrono::steady_clock;
 
+// Most iterations a wide run (LEVELS executor) advances per step when steps are sized in levels.
+constexpr int32_t kWideStepIters = 32;
+
 namespace {
 
 struct Request {
@@ -123,6 +126,13 @@ void fastlbp_server::loop() {
     (void)hipSetDevice(opts.device);
     std::vector<fastlbp_graph *> gs, narrow, wide;
     std::vector<double> damp, narrow_damp;
+    std::vector<int32_t> narrow_step, maxit;
+    // iterations a run advances per step: about step_levels levels (so a step costs about the same
+    // for every run and small graphs are not held back by large ones), or step_iters
+    auto iters_of = [&](int32_t units, int32_t max_iters) {
+        if (opts.step_levels <= 0) return opts.step_iters;
+        return std::max<int32_t>(1, std::min<int32_t>(std::max<int32_t>(1, max_iters), opts.step_levels / std::max(1, units)));
+    };
     while (true) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -178,9 +188,11 @@ void fastlbp_server::loop() {
             peak_resident = std::max(peak_resident, resident_bytes());
             gs.clear();
             damp.clear();
+            maxit.clear();
             for (auto &a : active) {
                 gs.push_back(a->g);
                 damp.push_back(a->damping);
+                maxit.push_back(a->max_iters);
             }
         }
         if (gs.empty()) continue;
@@ -196,19 +208,23 @@ void fastlbp_server::loop() {
             narrow.clear();
             wide.clear();
             narrow_damp.clear();
+            narrow_step.clear();
             for (size_t i = 0; i < gs.size(); ++i) {
                 if (graph_wide(gs[i])) {
                     wide.push_back(gs[i]);
-                    step_levels_enqueue(gs[i], damp[i], opts.step_iters);
+                    // (at most kWideStepIters: each handle captures its step's iterations in a hipGraph)
+                    step_levels_enqueue(gs[i], damp[i],
+                                        std::min(kWideStepIters, iters_of(graph_launches_per_iter(gs[i]), maxit[i])));
                 } else {
                     narrow.push_back(gs[i]);
                     narrow_damp.push_back(damp[i]);
+                    narrow_step.push_back(iters_of(graph_exec_levels(gs[i]), maxit[i]));
                 }
             }
             if (!narrow.empty()) {
                 std::vector<int32_t> it0(narrow.size());
                 for (size_t i = 0; i < narrow.size(); ++i) it0[i] = graph_host_state(narrow[i]).iter;
-                step_run(*launcher, int(narrow.size()), narrow.data(), narrow_damp.data(), opts.step_iters);
+                step_run(*launcher, int(narrow.size()), narrow.data(), narrow_damp.data(), narrow_step.data());
                 dev_ms = launcher_kernel_ms(launcher);
                 // method bytes of this persistent launch: each run's iterations in it
                 double bytes = 0.0;
@@ -285,6 +301,7 @@ void fastlbp_server_options_default(fastlbp_server_options *o) {
     o->max_active = 256;
     o->step_iters = 2;
     o->memory_budget = 0;
+    o->step_levels = 4096;
 }
 
 int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *out) {
@@ -297,8 +314,9 @@ int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *
     fastlbp_server_options o;
     fastlbp_server_options_default(&o);
     if (opts) o = *opts;
-    if (o.max_active < 1 || o.step_iters < 1 || (o.precision != FASTLBP_FP32 && o.precision != FASTLBP_FP64)) {
-        set_error("need max_active >= 1, step_iters >= 1 and a valid precision");
+    if (o.max_active < 1 || o.step_iters < 1 || o.step_levels < 0 ||
+        (o.precision != FASTLBP_FP32 && o.precision != FASTLBP_FP64)) {
+        set_error("need max_active >= 1, step_iters >= 1, step_levels >= 0 and a valid precision");
         return FASTLBP_E_INVALID_ARG;
     }
     std::unique_ptr<fastlbp_server> s(new fastlbp_server());
