@@ -50,8 +50,15 @@ TRAFFIC_DEFAULT = {"sources_sha256": "31b4714cb3264526fd0ef41714495d8f5ea68d7111
 
 # The same for the serving configuration (512 graphs, 512 active runs, 8 iterations per launch):
 # average k_persistent launch of the server. Empty until profiled.
-TRAFFIC_SERVING = {"sources_sha256": "", "bytes_per_launch": None, "queries": 512, "max_active": 512,
-                   "step_iters": 8}
+# Measured L2-to-fabric bytes of one k_persistent launch of the serving bench (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, KiB per dispatch, averaged over the profiled command's launches and scaled by the copy
+# calibration: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE). A serving launch holds whatever runs are in
+# flight, so the profiled launches carried their own method bytes (`method_bytes_per_launch`), listed
+# for comparison with the traffic.
+TRAFFIC_SERVING = {"sources_sha256": "a58ade30871af06b4ddbd1e81751273cb5ff7c6d7809e66c533c1d279b0b673b",
+                   "bytes_per_launch": 5157236605, "fetch_bytes_per_launch": 4141059326,
+                   "write_bytes_per_launch": 1016177279, "method_bytes_per_launch": 1968544857,
+                   "queries": 512, "max_active": 512, "step_iters": 8}
 
 
 def kernel_sources_sha256() -> str:
@@ -254,7 +261,7 @@ def serving_mix(F, W, args):
     n64 = min(args.fp64_graphs, len(qs))
     if n64 == 0:  # profiling runs: the batched FP32 server only
         return qs, res, dict(runs=len(res), wall_s=round(wall, 3), mups=round(upd / wall, 1), latency=dict(all=_lat(res)),
-                             server=sd, prefix=dict(latency={}), plain_fp64={}, fp32_error={})
+                             server=sd, prefix=dict(latency={}), plain_fp64=dict(latency={}), fp32_error={})
     r64, wall64, upd64, busy64 = _fifo_fp64(F, qs, clamps, n64)
     log(f"plain fp64 FIFO on the first {n64} graphs: {len(r64)} runs in {wall64:.2f} s, "
         f"{upd64 / busy64 / 1e6:.1f} M updates/s busy, p50 {_lat(r64)['p50_ms']} ms p99 {_lat(r64)['p99_ms']} ms")
@@ -284,9 +291,12 @@ def serving_mix(F, W, args):
                         service_p50_ms=pct([r["service_ms"] for r in r64], 50),
                         note="FIFO single-graph FP64 server (fastlbp_run one graph at a time) on the stream's "
                              "first graphs, same arrival times and re-query clamps; latency includes queueing"),
-        fp32_error=dict(vs="FP64 marginals of the same runs (plain FP64 leg)", runs=len(errs),
-                        max_abs=max(errs) if errs else None, runs_both_converged=len(errs_conv),
-                        max_abs_both_converged=max(errs_conv) if errs_conv else None),
+        fp32_error=dict(vs="FP64 marginals of the same runs (plain FP64 leg), runs where both converged",
+                        runs=len(errs_conv), max_abs=max(errs_conv) if errs_conv else None,
+                        runs_not_both_converged=len(errs) - len(errs_conv),
+                        max_abs_not_both_converged=max((e for e in errs if e not in errs_conv), default=None),
+                        note="a run that stops at max_iters without converging may end at another point of an "
+                             "oscillation in each precision; those runs are listed apart"),
         prefix_updates=upd_pre)
     return qs, res, out
 
@@ -627,10 +637,12 @@ def main():
         per_launch = sd["persistent_method_bytes"] / launches
         achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
         T = TRAFFIC_SERVING
-        traffic = None
+        traffic, traffic_detail = None, None
         if (args.queries == T["queries"] and args.batch == T["max_active"] and args.step_iters == T["step_iters"]
                 and args.seed == 0 and kernel_sources_sha256() == T["sources_sha256"]):
             traffic = T["bytes_per_launch"]
+            traffic_detail = {k: T[k] for k in ("fetch_bytes_per_launch", "write_bytes_per_launch",
+                                                "method_bytes_per_launch")}
         p64 = rs["plain_fp64"]
         out = {
             "metric": "message updates/sec (f->v) + p50/p99 query latency, batched FP32 vs plain FP64 BP",
@@ -651,7 +663,7 @@ def main():
                          "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                          "kernel": "k_persistent<PolLog32> (the narrow runs' launch of each server step)",
                          "launches": sd["persistent_launches"], "avg_launch_ms": round(avg_ms, 4),
-                         "method_bytes_per_launch": per_launch,
+                         "method_bytes_per_launch": per_launch, "traffic_profiled_launches": traffic_detail,
                          "kernel_share_of_device_ms": round(sd["persistent_ms"] / max(1e-9, sd["kernel_ms"]), 3),
                          "bytes_note": "method bytes: per touched factor edge 4 + 3s, per written edge 2s (tol > 0), "
                                        "s per NOISY_OR activation, s = 4 (FP32); times each run's iterations in the "

@@ -197,9 +197,11 @@ __host__ __device__ constexpr size_t stage_bytes(int32_t cap) {
 }
 
 // Levels [L0, L1) of one run in one workgroup of NT threads, with workgroup barriers between
-// phases. Thread tasks come as records whose loads are issued one phase ahead (the variable records
-// of a level while its factor phase runs, the factor records of the next level while the variable
-// phase runs), so each phase waits for one round of dependent loads. On entry `fr` / `pr` hold this
+// phases. Thread tasks come as records whose loads are issued ahead: a staged level's variable
+// records before its factor phase, the next level's records as soon as this level's factor phase
+// has issued its work, so their latency overlaps the barrier and the variable phase. Records are
+// read through the caches: a narrow run reads the same records every iteration, and its plan is
+// small enough to stay in the MALL (the wide-level kernels stream theirs). On entry `fr` / `pr` hold this
 // thread's first factor record of L0 and, if L0 is staged, its first two staged variable records
 // (tid and tid + NT); on exit they hold those of level `Lnext` (none when Lnext < 0). TEAMS adds the wavefront- and
 // workgroup-per-factor paths and the weighted-term paths. foff / voff / staged give each level's
@@ -223,11 +225,11 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         // reads LDS only: its records were prefetched, its beliefs come from the factor phase)
         VarRec vr = {};
         const VarRecP pc0 = pr[0], pc1 = pr[1];
-        if (v0 + tid < v1 && !stg) vr = vrec.ld_stream(v0 + tid);
+        if (v0 + tid < v1 && !stg) vr = vrec.ld(v0 + tid);
         S *const slots = stg ? s_slot : nullptr;
         if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots, b_slot);
         for (int32_t i = f0 + tid + NT; i < f1; i += NT)
-            factor_rec<P, DAMP>(g, frec.ld_stream(i), acc, slots, b_slot);
+            factor_rec<P, DAMP>(g, frec.ld(i), acc, slots, b_slot);
         if (TEAMS) {
             const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
             int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
@@ -235,7 +237,7 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         }
         if (TEAMS) {
             const int32_t o0 = plan.trec_off[L], o1 = plan.trec_off[L + 1];
-            for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_rec<P, DAMP>(g, plan.trec.ld_stream(i), acc);
+            for (int32_t i = o0 + tid; i < o1; i += NT) factor_terms_rec<P, DAMP>(g, plan.trec.ld(i), acc);
         }
         if (TEAMS) {
             const GPtr<const int32_t> lst = plan.fac_list[FB_TERMS_WAVE];
@@ -248,15 +250,6 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
             for (int32_t i = o0; i < o1; ++i)
                 factor_team<P, NT, (kBlockMaxDeg - 1) / NT, false, DAMP>(g, lst[i], tid, L, acc, lds);
         }
-        if (stg) {
-            // the variable phase reads only the staging slots and beliefs loaded before the
-            // level: wait for LDS, not for the messages' global stores
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-            __builtin_amdgcn_s_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-        } else {
-            __syncthreads();
-        }
         {
             // records of the next level (Lnext after the last level of the range)
             // UNCOND: unconditional loads, record 0 for threads without one (never used: the phases
@@ -266,30 +259,39 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
             if (UNCOND) {
                 if (Ln >= 0) {
                     const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
-                    fr = frec.ld_stream(n0 + tid < n1 ? n0 + tid : 0);
+                    fr = frec.ld(n0 + tid < n1 ? n0 + tid : 0);
                     const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                    pr[0] = prec.ld_stream(staged(Ln) && m0 + tid < m1 ? m0 + tid : 0);
-                    pr[1] = prec.ld_stream(staged(Ln) && m0 + tid + NT < m1 ? m0 + tid + NT : 0);
+                    pr[0] = prec.ld(staged(Ln) && m0 + tid < m1 ? m0 + tid : 0);
+                    pr[1] = prec.ld(staged(Ln) && m0 + tid + NT < m1 ? m0 + tid + NT : 0);
                 }
             } else {
                 fr = FacRec{};
                 pr[0] = pr[1] = VarRecP{};
                 if (Ln >= 0) {
                     const int32_t n0 = foff(Ln), n1 = foff(Ln + 1);
-                    if (n0 + tid < n1) fr = frec.ld_stream(n0 + tid);
+                    if (n0 + tid < n1) fr = frec.ld(n0 + tid);
                     const int32_t m0 = voff(Ln), m1 = voff(Ln + 1);
-                    if (staged(Ln) && m0 + tid < m1) pr[0] = prec.ld_stream(m0 + tid);
-                    if (staged(Ln) && m0 + tid + NT < m1) pr[1] = prec.ld_stream(m0 + tid + NT);
+                    if (staged(Ln) && m0 + tid < m1) pr[0] = prec.ld(m0 + tid);
+                    if (staged(Ln) && m0 + tid + NT < m1) pr[1] = prec.ld(m0 + tid + NT);
                 }
             }
         }
         if (stg) {
+            // the variable phase reads only the staging slots and beliefs loaded before the
+            // level: wait for LDS, not for the messages' global stores
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        } else {
+            __syncthreads();
+        }
+        if (stg) {
             if (v0 + tid < v1) var_staged<P>(g, pc0, s_slot, b_slot);
             if (v0 + tid + NT < v1) var_staged<P>(g, pc1, s_slot, b_slot);
-            for (int32_t i = v0 + tid + 2 * NT; i < v1; i += NT) var_staged<P>(g, prec.ld_stream(i), s_slot, b_slot);
+            for (int32_t i = v0 + tid + 2 * NT; i < v1; i += NT) var_staged<P>(g, prec.ld(i), s_slot, b_slot);
         } else {
             if (v0 + tid < v1) var_rec<P>(g, vr);
-            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld_stream(i));
+            for (int32_t i = v0 + tid + NT; i < v1; i += NT) var_rec<P>(g, vrec.ld(i));
             const GPtr<const int32_t> lst = plan.var_list[VB_WAVE];
             int32_t o0 = plan.var_lvl_off[VB_WAVE][L], o1 = plan.var_lvl_off[VB_WAVE][L + 1];
             for (int32_t i = o0 + w; i < o1; i += NW) var_wave<P>(g, lst[i], lane);
@@ -354,9 +356,9 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     FacRec fr = {};
     VarRecP pr[2] = {};
     if (NL > 0) {
-        fr = frec.ld_stream(foff(0) + tid < foff(1) ? foff(0) + tid : 0);
-        pr[0] = prec.ld_stream(staged(0) && voff(0) + tid < voff(1) ? voff(0) + tid : 0);
-        pr[1] = prec.ld_stream(staged(0) && voff(0) + tid + NT < voff(1) ? voff(0) + tid + NT : 0);
+        fr = frec.ld(foff(0) + tid < foff(1) ? foff(0) + tid : 0);
+        pr[0] = prec.ld(staged(0) && voff(0) + tid < voff(1) ? voff(0) + tid : 0);
+        pr[1] = prec.ld(staged(0) && voff(0) + tid + NT < voff(1) ? voff(0) + tid + NT : 0);
     }
     while (!s_done) {
         Acc acc = {0.0, 0u};
@@ -421,9 +423,9 @@ __global__ __launch_bounds__(NT) void k_levels_fused(DevGraph<typename P::S, typ
     auto staged = [&](int32_t L) { return staging && plan.level_lds[L] != 0; };
     FacRec fr = {};
     VarRecP pr[2] = {};
-    if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld_stream(foff(L0) + tid);
-    if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr[0] = plan.prec.ld_stream(voff(L0) + tid);
-    if (staged(L0) && voff(L0) + tid + NT < voff(L0 + 1)) pr[1] = plan.prec.ld_stream(voff(L0) + tid + NT);
+    if (foff(L0) + tid < foff(L0 + 1)) fr = plan.frec.ld(foff(L0) + tid);
+    if (staged(L0) && voff(L0) + tid < voff(L0 + 1)) pr[0] = plan.prec.ld(voff(L0) + tid);
+    if (staged(L0) && voff(L0) + tid + NT < voff(L0 + 1)) pr[1] = plan.prec.ld(voff(L0) + tid + NT);
     Acc acc = {0.0, 0u};
     level_range<P, DAMP, TEAMS, NT, false>(g, plan, L0, L1, -1, foff, voff, staged, s_slot, b_slot, &lds, acc, fr, pr);
     flush_acc<NT>(acc, st);

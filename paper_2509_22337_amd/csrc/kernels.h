@@ -80,6 +80,13 @@ struct PolLog32 {
         const float pl = lo == -INFINITY ? 0.0f : __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-lo));
         return (double)(ph - pl);
     }
+    // An upper bound of delta_p1(a, b) that costs no transcendental: the slope of P(x=1) in the LLR
+    // (bits) is ln2 P (1 - P) <= ln2 / 4 = 0.1732868; 0.1734 leaves room for delta_p1's own rounding
+    // (a few ulp relative). Equal infinities (a - b = NaN) give 0, as delta_p1 does.
+    static __device__ __forceinline__ double delta_bound(S a, S b) {
+        const float d = fabsf(a - b);
+        return d > 0.0f ? (double)(d * 0.1734f) : 0.0;
+    }
 };
 
 // float64, linear domain.
@@ -108,6 +115,12 @@ struct PolLin64 {
     static __device__ __forceinline__ S from_double(double x) { return x; }
     static __device__ __forceinline__ double delta_p1(S a, S b) {
         return fabs(1.0 / (1.0 + exp2(-a)) - 1.0 / (1.0 + exp2(-b)));
+    }
+    // Upper bound of delta_p1(a, b) (slope of P(x=1) in the LLR at most ln2 / 4), with an absolute
+    // margin for the rounding of the difference of two probabilities.
+    static __device__ __forceinline__ double delta_bound(S a, S b) {
+        const double d = fabs(a - b);
+        return d > 0.0 ? d * 0.1734 + 1e-15 : 0.0;
     }
 };
 
@@ -228,7 +241,8 @@ __device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S
         l = P::llr(P::add(P::mul(g.damp_old, a0), P::mul(g.damp_new, b0)),
                    P::add(P::mul(g.damp_old, a1), P::mul(g.damp_new, b1)), c2);
     }
-    acc.r = fmax(acc.r, P::delta_p1(l, old));
+    // the residual is a maximum: a change whose bound cannot raise it needs no exact value
+    if (P::delta_bound(l, old) > acc.r) acc.r = fmax(acc.r, P::delta_p1(l, old));
     return l;
 }
 
