@@ -1,27 +1,25 @@
 """Benchmark: factor-to-variable message updates per second and query latency of belief
 propagation on one MI355X, batched FP32 vs plain FP64.
 
-Workload: the SmartFL-shaped graph. It has 200,000 binary variables in 500 layers, one
-deterministic AND/OR/NOT factor per variable over 1-4 predecessors (Zipf), Beta(9,1) priors and a
-forward-backward (TOPO) ranked schedule. The dependency analysis splits it into 998 levels. It runs
-with tol 1e-6 and up to 500 iterations.
+Default workload (--workload serving): 512 graphs of 1k-500k variables (log-uniform), half
+Datalog-shaped (flooding, damping 0.5) and half SmartFL-shaped (forward-backward ranked schedule,
+2% clamps), arriving as a Poisson process at 200 queries/s; each query is re-submitted warm with
+1-10 new clamps when it completes (1,024 runs), tol 1e-6, at most 100 iterations.
 
-A query clamps 2% of the variables to a consistent world (a different seeded set per query),
-starts from uniform messages and runs until the residual falls below tol or max_iters is reached.
-It then reads back the marginals. Most evidence sets keep the forward-backward schedule
-oscillating, so those queries run to max_iters.
+* step (timed): one run of the stream on the FP32 continuous-batching server. `value` is the FP32
+  message updates of all runs over the wall time of the whole stream (inputs resident; clamps in
+  and marginals out cross PCIe inside the timed region).
+* plain FP64: a FIFO server running one FP64 graph at a time on the same arrival stream (a prefix
+  of the stream), latency including queueing; the FP32 server's latencies on the same prefix.
+* fp32_error: FP32 marginals against the FP64 ones of the same runs.
+* roofline: the persistent kernel of the server's steps: method bytes of the runs it advanced over
+  its launch time (HIP events on the server's stream).
+* cpu_baseline: the FP64 oracle on one host thread, cold runs of the prefix's smallest graphs.
+* extra: the saturated narrow-level kernel (512 batched queries of the 200k-variable SmartFL-shaped
+  graph) and the wide-level kernels (the 19M-edge BINGO-shaped graph, flooding), each with its own
+  roofline.
 
-* step (timed): a batch of --batch queries submitted together to the FP32 continuous-batching
-  server (one workgroup per running query, --step-iters iterations per launch, queries retire as
-  they finish). `value` is the FP32 message updates per second over the timed steps.
-* plain FP64: --fp64-queries of the same queries, one after another, each a single-graph FP64 run.
-* solo FP32: the first query alone (unbatched FP32), for the latency of one query.
-* roofline: the persistent kernel of the batched steps. Its algorithmic bytes (the library's exact
-  per-iteration count times iterations, summed over queries) are divided by the summed kernel time,
-  measured with HIP events on the server's stream.
-* cpu_baseline: the FP64 oracle on one host thread, a bounded number of full iterations of the same
-  graph and schedule.
-
+Other workloads: smartfl (batched queries of one graph), bingo, bingo-terms, bingo-large, alarms.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -564,6 +562,44 @@ def serving_cpu_baseline(qs, runs, budget_s: float, n_prefix: int):
                 runs_compared=len(errs))
 
 
+def extra_workloads(F, W, args):
+    """Two more lines of the default run, beside the serving stream: the saturated narrow-level
+    kernel (512 batched queries of the 200k-variable SmartFL-shaped graph, one warm-up and one
+    timed step) and the wide-level kernels (the 19M-edge BINGO-shaped graph, flooding, 100
+    iterations, FP32 and FP64)."""
+    import torch
+    out = {}
+    w = W.smartfl(args.seed)
+    queries = [query_evidence(w, q) for q in range(512)]
+    log(f"extra: smartfl batched, {len(queries)} queries per step")
+    rb = batched_steps(F, w, queries, 1, 1, 8)
+    launches = max(1, rb["launches"])
+    avg_ms = rb["kernel_ms"] / launches
+    per_launch = rb["alg_bytes"] / launches
+    ach = per_launch / (avg_ms / 1e3) / 1e9
+    out["smartfl_batched"] = {
+        "workload": "smartfl_200k_vars_500_layers_fwd_bwd_ranked, 512 queries per step (2% clamps each), fp32",
+        "mups": round(rb["updates"] / rb["wall_s"], 1), "device_mups": round(rb["updates"] / (rb["kernel_ms"] / 1e3), 1),
+        "ms_per_step": round(rb["wall_s"] * 1e3, 3), "p50_ms": pct(rb["lat_ms"], 50), "p99_ms": pct(rb["lat_ms"], 99),
+        "iterations_p50": int(np.median(rb["iters"])),
+        "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 5), "kernel": "k_persistent<PolLog32> (512 threads, 2 queries per CU)",
+                     "launches": rb["launches"], "avg_launch_ms": round(avg_ms, 4), "method_bytes_per_launch": per_launch}}
+    del rb
+    torch.cuda.empty_cache()
+    wb = W.config("C3", seed=args.seed)
+    log(f"extra: bingo flooding V={wb.num_vars} E={wb.num_edges}")
+    res = {prec: flooding_runs(F, wb, prec, 1, 1 if prec == "fp32" else 0, 100, "bingo") for prec in ("fp32", "fp64")}
+    r = res["fp32"]
+    out["bingo_flooding"] = {
+        "workload": "bingo_2M_tuples_4M_rules_19M_edges_flooding, 100 iterations, fp32 (fp64 for the error)",
+        "mups": round(r["updates"] / r["wall_s"], 1), "us_per_iteration": r["us_per_iteration"],
+        "plain_fp64_us_per_iteration": res["fp64"]["us_per_iteration"],
+        "fp32_error_max_abs": float(np.abs(r["marginals"] - res["fp64"]["marginals"]).max()),
+        "roofline": _roofline_levels(r, "one iteration of the LEVELS executor (all kernels)")}
+    return out
+
+
 def pct(a, q):
     return round(float(np.percentile(a, q)), 3)
 
@@ -583,6 +619,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help="only the batched FP32 steps (profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="serving: skip the extra lines (batched SmartFL-shaped queries, BINGO-shaped flooding)")
     ap.add_argument("--alarms", type=int, default=300, help="alarms of the alarm-ranking workload")
     ap.add_argument("--workload", choices=["smartfl", "serving", "bingo", "bingo-terms", "bingo-large", "alarms"],
                     default="serving",
@@ -672,6 +710,8 @@ def main():
         }
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = serving_cpu_baseline(qs, runs, args.cpu_budget, args.fp64_graphs)
+        if not args.serving_only:
+            out["extra"] = extra_workloads(F, W, args)
         print(json.dumps(out), flush=True)
         return
     w = W.smartfl(args.seed)

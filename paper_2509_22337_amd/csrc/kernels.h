@@ -722,7 +722,15 @@ __device__ __forceinline__ void stage_slot(typename P::S *slots, int32_t slot0, 
     }
 }
 
-template <class P, bool DAMP, int D>
+// Factor families of the thread path, fixed at compile time so that a wavefront (whose records
+// share degree and type) runs straight-line code. FAM_OR covers OR, AND and NOT: AND is OR on the
+// negated edges (y = AND(x) iff not y = OR(not x)) and NOT is a one-input OR on its negated input,
+// so those edges enter as negated LLRs and their two message entries leave swapped. Swapping the
+// pair is exactly the negation the AND and NOT formulas perform, so every stored value equals the
+// one the type's own formula gives.
+enum { FAM_OR = 0, FAM_IMPLIES = 1, FAM_NOISY = 2 };
+
+template <class P, bool DAMP, int D, int FAM>
 __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int32_t b,
                                              unsigned active, const Pair<typename P::V> &fp,
                                              const typename P::S (&lo)[D], const typename P::S (&vf)[D],
@@ -730,74 +738,154 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
                                              typename P::S *slots, int32_t slot0) {
     using S = typename P::S;
     using V = typename P::V;
-    if constexpr (D == 2) {
-        if (type == T_NOT) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (!((active >> k) & 1u)) continue;
-                V m0, m1;
-                P::leaf(-vf[1 - k], m0, m1);
-                const S l = finish_msg<P, DAMP>(g, lo[k], m0, m1, nl[1 - k], acc);
-                put_msg(g, b + k, l, lo[k]);
-                stage_slot<P>(slots, slot0, active, k, l, lo[k]);
-            }
-            return;
-        }
-    }
     constexpr int n = D - 1;
-    V my0 = P::zero(), my1 = P::zero();
-    if (!nl[n]) P::leaf(vf[n], my0, my1);
+    // edges entering negated (FAM_OR only): AND every edge, NOT its input
+    const unsigned flip = FAM != FAM_OR ? 0u : type == T_AND ? (1u << D) - 1u : type == T_NOT ? 1u : 0u;
     HF<V> lf[n];
     int nnull = 0;
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-        lf[k] = identity<P>();
-        if (!nl[k]) {
-            V m0, m1;
-            P::leaf(vf[k], m0, m1);
-            lf[k] = make_leaf<P>(type, m0, m1, ep[k]);
-        } else {
-            ++nnull;
-        }
+        V m0, m1;
+        P::leaf(((flip >> k) & 1u) ? -vf[k] : vf[k], m0, m1);
+        HF<V> x;
+        if constexpr (FAM == FAM_OR) x = {m0, m1};
+        else if constexpr (FAM == FAM_NOISY) x = {P::add(m0, P::mul(m1, ep[k].b)), P::mul(m1, ep[k].a)};
+        else x = {m1, m0};  // IMPLIES: an input fires when it is 0
+        // a null incoming message contributes the identity leaf
+        lf[k].h = nl[k] ? P::one() : x.h;
+        lf[k].f = nl[k] ? P::zero() : x.f;
+        nnull += nl[k] ? 1 : 0;
     }
+    // Products with the identity leaf are skipped: combining with (1, 0) returns the other operand
+    // exactly (log domain: x + 0 and log2(2^x + 0) = x), so only the NOISY_OR leak (the leftmost
+    // leaf) costs a combine at the ends of the prefix and suffix products.
     HF<V> pre = identity<P>();
-    if (type == T_NOISY_OR) pre = {fp.b, fp.a};  // leak
-    HF<V> tot = pre;
-#pragma unroll
-    for (int k = 0; k < n; ++k) tot = combine<P>(tot, lf[k]);
+    if constexpr (FAM == FAM_NOISY) pre = {fp.b, fp.a};  // leak
+    HF<V> l0 = lf[0];  // prefix product through input 0, leak included
+    if constexpr (FAM == FAM_NOISY) l0 = combine<P>(pre, lf[0]);
+    // Each part below runs only when the task writes an edge that needs it. Under a ranked
+    // schedule a task usually writes either the head (forward) or the inputs (backward), and the
+    // records of a level mostly agree, so the wavefront skips the other part.
     if ((active >> n) & 1u) {
+        HF<V> t = l0;
+#pragma unroll
+        for (int k = 1; k < n; ++k) t = combine<P>(t, lf[k]);
         V o0, o1;
-        head_msg<P>(type, tot, fp, o0, o1);
+        if constexpr (FAM == FAM_IMPLIES) {  // fp = (p, 1-p)
+            o0 = P::add(P::mul(fp.b, t.h), t.f);
+            o1 = P::add(P::mul(fp.a, t.h), t.f);
+        } else {
+            o0 = t.h;
+            o1 = t.f;
+        }
+        if ((flip >> n) & 1u) {
+            const V tmp = o0;
+            o0 = o1;
+            o1 = tmp;
+        }
         const S l = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
         put_msg(g, b + n, l, lo[n]);
         stage_slot<P>(slots, slot0, active, n, l, lo[n]);
     }
-    HF<V> sx[n];
-    HF<V> run = identity<P>();
+    if (active & ((1u << n) - 1u)) {
+        // the head's normalised incoming message (zero when null)
+        V my0, my1;
+        P::leaf(((flip >> n) & 1u) ? -vf[n] : vf[n], my0, my1);
+        my0 = nl[n] ? P::zero() : my0;
+        my1 = nl[n] ? P::zero() : my1;
+        // sx[k] = product of the leaves after input k (k <= n - 2; after the last one: identity)
+        HF<V> sx[n];
+        if constexpr (n >= 2) {
+            sx[n - 2] = lf[n - 1];
 #pragma unroll
-    for (int k = n - 1; k >= 0; --k) {
-        sx[k] = run;
-        run = combine<P>(lf[k], run);
-    }
-    run = pre;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        if ((active >> k) & 1u) {
-            HF<V> xo = combine<P>(run, sx[k]);
-            V o0, o1;
-            input_msg<P>(type, xo, my0, my1, fp, ep[k], o0, o1);
-            int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
-            const S l = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
-            put_msg(g, b + k, l, lo[k]);
-            stage_slot<P>(slots, slot0, active, k, l, lo[k]);
+            for (int k = n - 3; k >= 0; --k) sx[k] = combine<P>(lf[k + 1], sx[k + 1]);
         }
-        run = combine<P>(run, lf[k]);
+        HF<V> run = l0;  // prefix product through input k - 1 (for k >= 1)
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            if ((active >> k) & 1u) {
+                HF<V> x;  // product of the other inputs' leaves, leak included
+                if (k == 0) {
+                    if constexpr (n == 1) {
+                        x = pre;
+                    } else {
+                        x = sx[0];
+                        if constexpr (FAM == FAM_NOISY) x = combine<P>(pre, sx[0]);
+                    }
+                } else if (k == n - 1) {
+                    x = run;
+                } else {
+                    x = combine<P>(run, sx[k]);
+                }
+                V o0, o1;
+                if constexpr (FAM == FAM_IMPLIES) {
+                    const V s2 = P::add(my0, my1);
+                    const V wy = P::add(P::mul(my0, fp.b), P::mul(my1, fp.a));
+                    o0 = s2;
+                    o1 = P::add(P::mul(wy, x.h), P::mul(s2, x.f));
+                } else {
+                    const V base = P::add(P::mul(my0, x.h), P::mul(my1, x.f));  // input k does not fire
+                    o0 = base;
+                    if constexpr (FAM == FAM_NOISY) o1 = P::add(P::mul(ep[k].b, base), P::mul(ep[k].a, my1));
+                    else o1 = my1;
+                }
+                if ((flip >> k) & 1u) {
+                    const V tmp = o0;
+                    o0 = o1;
+                    o1 = tmp;
+                }
+                const int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
+                const S l = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
+                put_msg(g, b + k, l, lo[k]);
+                stage_slot<P>(slots, slot0, active, k, l, lo[k]);
+            }
+            if (k >= 1 && k + 1 < n) run = combine<P>(run, lf[k]);
+        }
     }
 }
 
-// Loads of one factor of degree D (edges b .. b+D-1, variables u[]), all issued before any is used.
-// On a level staged in LDS, the belief of each written edge's variable (as the factor read it, the
-// value before the level) also goes to the edge's slot in bslots, for the variable phase.
+// N consecutive values from p (global memory, 4-byte aligned) in as few loads as possible: 16-byte
+// loads, then one of 4, 8 or 12 bytes for the rest. A factor's messages are contiguous, so a thread
+// fetches them with one or two requests instead of one per edge.
+template <class S, int N>
+__device__ __forceinline__ void load_run(const S *p, S (&out)[N]) {
+    typedef int iv4 __attribute__((ext_vector_type(4), aligned(4)));
+    typedef int iv3 __attribute__((ext_vector_type(3), aligned(4)));
+    typedef int iv2 __attribute__((ext_vector_type(2), aligned(4)));
+    typedef __attribute__((address_space(1))) const int gint;
+    typedef __attribute__((address_space(1))) const iv4 giv4;
+    typedef __attribute__((address_space(1))) const iv3 giv3;
+    typedef __attribute__((address_space(1))) const iv2 giv2;
+    static_assert(sizeof(S) % 4 == 0, "dword-sized values only");
+    constexpr int NW = N * int(sizeof(S) / 4);
+    int w[NW];
+    gint *q = (gint *)p;
+#pragma unroll
+    for (int i = 0; i + 4 <= NW; i += 4) {
+        const iv4 x = *(giv4 *)(q + i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[i + j] = x[j];
+    }
+    constexpr int R = NW % 4, B0 = NW - R;
+    if constexpr (R == 3) {
+        const iv3 x = *(giv3 *)(q + B0);
+        w[B0] = x[0];
+        w[B0 + 1] = x[1];
+        w[B0 + 2] = x[2];
+    } else if constexpr (R == 2) {
+        const iv2 x = *(giv2 *)(q + B0);
+        w[B0] = x[0];
+        w[B0 + 1] = x[1];
+    } else if constexpr (R == 1) {
+        w[B0] = q[B0];
+    }
+    __builtin_memcpy(out, w, sizeof(out));
+}
+
+// Loads of one factor of degree D (edges b .. b+D-1, variables u[]), all issued before any is used,
+// then the family's arithmetic. On a level staged in LDS, the belief of each written edge's
+// variable (as the factor read it, the value before the level) also goes to the edge's slot in
+// bslots, for the variable phase.
 template <class P, bool DAMP, int D>
 __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
                                                      int type, int32_t fac, unsigned active, const int32_t *u,
@@ -806,20 +894,20 @@ __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::
     using V = typename P::V;
     S lo[D];
     Belief B[D];
+    load_run<S, D>(g.msg.get() + b, lo);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        lo[k] = g.msg[b + k];
-        B[k] = g.bel.ld(u[k]);
-    }
+    for (int k = 0; k < D; ++k) B[k] = g.bel.ld(u[k]);
     Pair<V> ep[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) ep[k] = {P::zero(), P::one()};
-    if (type == T_NOISY_OR) {
-#pragma unroll
-        for (int k = 0; k < D - 1; ++k) ep[k] = g.epar.ld(b + k);
-    }
     Pair<V> fp = {P::zero(), P::one()};
-    if (type == T_NOISY_OR || type == T_IMPLIES) fp = g.fpar.ld(fac);
+    if (type == T_NOISY_OR || type == T_IMPLIES) {
+        fp = g.fpar.ld(fac);
+        if (type == T_NOISY_OR) {
+#pragma unroll
+            for (int k = 0; k < D - 1; ++k) ep[k] = g.epar.ld(b + k);
+        }
+    }
     S vf[D];
     bool nl[D];
 #pragma unroll
@@ -829,7 +917,12 @@ __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::
         for (int k = 0; k < D; ++k)
             if ((active >> k) & 1u) bslots[slot0 + __builtin_popcount(active & ((1u << k) - 1u))] = B[k];
     }
-    factor_local<P, DAMP, D>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+    if (type == T_NOISY_OR)
+        factor_local<P, DAMP, D, FAM_NOISY>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+    else if (type == T_IMPLIES)
+        factor_local<P, DAMP, D, FAM_IMPLIES>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+    else
+        factor_local<P, DAMP, D, FAM_OR>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
 }
 
 // `slots`: the level's LDS staging area (persistent executor, staged levels), else nullptr.
