@@ -657,16 +657,16 @@ __device__ __forceinline__ void factor_terms_rec(const DevGraph<typename P::S, t
 }
 
 // Variable phase: B_v = phi_v + sum of the v's incoming non-PRIOR messages (float64, with counts).
+// Branch-free (a wavefront's lanes disagree on which terms are infinite): an infinite term adds to
+// its count and 0 to the finite part.
 template <class P>
 __device__ __forceinline__ void belief_add(Belief &B, typename P::S l) {
     using S = typename P::S;
     const S inf = (S)__builtin_huge_val();
-    if (l == inf)
-        B.npos++;
-    else if (l == -inf)
-        B.nneg++;
-    else
-        B.fin += (double)l;
+    const bool pi = l == inf, ni = l == -inf;
+    B.npos += pi ? 1 : 0;
+    B.nneg += ni ? 1 : 0;
+    B.fin += (pi || ni) ? 0.0 : (double)l;
 }
 
 template <class P>
@@ -980,12 +980,10 @@ template <class P>
 __device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
     using S = typename P::S;
     const S inf = (S)__builtin_huge_val();
-    if (l == inf)
-        B.npos--;
-    else if (l == -inf)
-        B.nneg--;
-    else
-        B.fin -= (double)l;
+    const bool pi = l == inf, ni = l == -inf;
+    B.npos -= pi ? 1 : 0;
+    B.nneg -= ni ? 1 : 0;
+    B.fin -= (pi || ni) ? 0.0 : (double)l;
 }
 
 // Incremental variable task (LEVELS executor), from a record of the level's delta list: kind 0
