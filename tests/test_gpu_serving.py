@@ -171,3 +171,65 @@ def test_server_steps_hybrid_runs(precision):
         assert np.abs(m_srv - om).max() <= TOL[precision]
     for h in hs + solo:
         h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_server_serving_mix_generator(precision):
+    # the serving-mix generator (log-uniform sizes, half Datalog-shaped with flooding and damping,
+    # half SmartFL-shaped with forward-backward ranks, tol 1e-6, at most 100 iterations), scaled
+    # down: every query runs cold, then warm with the re-query clamps drawn from its own result.
+    # Served in one stream, every run equals the same run alone (same iterations, same marginals
+    # within rounding); runs the oracle brings to convergence also match the oracle
+    qs = W.serving_mix(3, num_queries=10, min_vars=1000, max_vars=12_000)
+    solo = [F.Graph.from_workload(q.graph, precision=precision) for q in qs]
+    for h in solo:
+        h.evidence_clear()
+    alone, clamps = [], []
+    for i, q in enumerate(qs):
+        h = solo[i]
+        h.evidence_set(q.ev_vars, q.ev_vals)
+        st = h.run(q.graph.max_iters, q.graph.tol, q.graph.damping)
+        m = h.marginals()
+        v, x = W.requery_clamps(q.graph, m, seed=500 + i)
+        clamps.append((v, x))
+        h.evidence_set(v, x)
+        st2 = h.run(q.graph.max_iters, q.graph.tol, q.graph.damping)
+        alone.append(((m, st), (h.marginals(), st2)))
+    srv = F.Server(precision=precision, max_active=6, step_iters=4)
+    hs = [F.Graph.from_workload(q.graph, precision=precision) for q in qs]
+    for h in hs:
+        h.evidence_clear()
+    cold = [srv.submit(hs[i], q.ev_vars, q.ev_vals, q.graph.max_iters, q.graph.tol, q.graph.damping)
+            for i, q in enumerate(qs)]
+    served = []
+    for i, q in enumerate(qs):  # a graph's warm re-query is submitted when its cold run completes
+        r1 = srv.wait(cold[i])
+        t2 = srv.submit(hs[i], clamps[i][0], clamps[i][1], q.graph.max_iters, q.graph.tol, q.graph.damping)
+        served.append((r1, t2))
+    served = [(r1, srv.wait(t2)) for r1, t2 in served]
+    srv.close()
+    n_oracle = 0
+    for i, q in enumerate(qs):
+        w = q.graph
+        ev = np.full(w.num_vars, -1, np.int8)
+        ev[q.ev_vars] = q.ev_vals
+        m0 = m1 = np.full(w.num_edges, 0.5)
+        for k in range(2):
+            if k == 1:
+                ev[clamps[i][0]] = clamps[i][1]
+            m_srv, st_srv, _ = served[i][k]
+            m_al, st_al = alone[i][k]
+            d_al = float(np.abs(m_srv - m_al).max())
+            om, m0, m1, ost = oracle.bp_pairs(w, m0, m1, w.max_iters, w.tol, w.damping, ranks=w.edge_rank,
+                                              evidence=ev)
+            d_or = float(np.abs(m_srv - om).max())
+            _say(precision, i, w.name, w.num_vars, "run", k, "iters", st_srv["iterations"], st_al["iterations"],
+                 ost["iterations"], "alone", d_al, "oracle", d_or, "converged", ost["converged"])
+            assert st_srv["iterations"] == st_al["iterations"]
+            assert d_al <= (1e-12 if precision == "fp64" else 1e-6)
+            if ost["converged"] and st_srv["converged"] and (k == 0 or alone[i][0][1]["converged"]):
+                assert d_or <= TOL[precision]
+                n_oracle += 1
+    assert n_oracle >= 4
+    for h in hs + solo:
+        h.close()
