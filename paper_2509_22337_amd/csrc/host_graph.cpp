@@ -552,12 +552,17 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
             // thread bucket: by degree, then type (a wavefront follows one code path), then factor
             // id, so neighbouring threads read neighbouring messages and, where the caller numbers
             // variables in factor order, neighbouring beliefs (ordering by first variable instead
-            // costs the 19M-edge BINGO-shaped graph 11% per iteration); wider buckets: largest
-            // first, so the longest tasks start early
+            // costs the 19M-edge BINGO-shaped graph 11% per iteration). A narrow level (one
+            // workgroup runs it) puts the highest degrees first: its time is that of its slowest
+            // wavefront, the one holding the largest factors, and the lowest wavefronts of a
+            // workgroup get their loads issued first (SmartFL-shaped graph: 5% per level). Wider
+            // buckets: largest first, so the longest tasks start early
             // (lists are built in factor order, and the sorts below are stable)
             if (b == FB_THREAD) {
-                counting_sort(src, int64_t(kThreadMaxDeg + 1) * 8,
-                              [&](int32_t x) { return int64_t(fdeg(x)) * 8 + g.fac_type[x]; }, sort_tmp);
+                const bool narrow = int64_t(src.size()) <= kFuseMaxRecs;
+                counting_sort(src, int64_t(kThreadMaxDeg + 1) * 8, [&](int32_t x) {
+                    return int64_t(narrow ? kThreadMaxDeg - fdeg(x) : fdeg(x)) * 8 + g.fac_type[x];
+                }, sort_tmp);
             } else if (b == FB_TERMS_THREAD)  // by degree, then term count: a wavefront's loops agree
                 std::sort(src.begin(), src.end(), [&](int32_t x, int32_t y) {
                     int dx = fdeg(x), dy = fdeg(y);
@@ -578,7 +583,12 @@ void HostPlan::build(const HostGraph &g, const std::vector<int32_t> &level, int3
         var_lvl_off[b].assign(1, 0);
         for (int32_t L = 0; L < exec_levels; ++L) {
             auto &src = var_by_level[L * VB_COUNT + b];
-            if (b == VB_THREAD) counting_sort(src, kVarRecEdges + 1, vkey, sort_tmp);
+            if (b == VB_THREAD) {  // by degree; on a narrow level the highest first, as for factors
+                const bool narrow = int64_t(src.size()) <= kFuseMaxRecs;
+                counting_sort(src, kVarRecEdges + 1,
+                              [&](int32_t v) { return narrow ? int64_t(kVarRecEdges - vkey(v)) : int64_t(vkey(v)); },
+                              sort_tmp);
+            }
             var_list[b].insert(var_list[b].end(), src.begin(), src.end());
             var_lvl_off[b].push_back(int32_t(var_list[b].size()));
         }
