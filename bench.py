@@ -37,25 +37,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# Measured HBM traffic of one k_persistent launch in the default configuration (512 queries, 8
-# iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
+# Measured HBM traffic of one k_persistent launch of the batched SmartFL-shaped queries (512 queries,
+# about 4 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "31b4714cb3264526fd0ef41714495d8f5ea68d711170594680c817201346c7b0",
-                   "bytes_per_launch": 206388724709.6, "raw_bytes_per_launch": 126011867136.0,
+TRAFFIC_DEFAULT = {"sources_sha256": "5f4d2fc8d2507a1254c8cbd26b673928feb7636805e728a05a08dd1045ecabe6",
+                   "bytes_per_launch": 62408424395.7, "raw_bytes_per_launch": 43959077887.5,
                    "queries": 512, "step_iters": 8}
 
 
-# The same for the serving configuration (512 graphs, 512 active runs, 8 iterations per launch):
-# average k_persistent launch of the server. Empty until profiled.
-# Measured L2-to-fabric bytes of one k_persistent launch of the serving bench (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, KiB per dispatch, averaged over the profiled command's launches and scaled by the copy
-# calibration: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE). A serving launch holds whatever runs are in
-# flight, so the profiled launches carried their own method bytes (`method_bytes_per_launch`), listed
-# for comparison with the traffic.
-TRAFFIC_SERVING = {"sources_sha256": "a58ade30871af06b4ddbd1e81751273cb5ff7c6d7809e66c533c1d279b0b673b",
-                   "bytes_per_launch": 5157236605, "fetch_bytes_per_launch": 4141059326,
-                   "write_bytes_per_launch": 1016177279, "method_bytes_per_launch": 1968544857,
+# The same for the serving configuration (512 graphs, up to 512 active runs): the average k_persistent
+# launch of the server (profiles/k_persistent_serving_mix_512_graphs.md; FETCH_SIZE x2.0, WRITE_SIZE
+# x1.0, KiB per dispatch averaged over the profiled command's launches). A serving launch holds
+# whatever runs are in flight, so the profiled launches carried their own method bytes
+# (`method_bytes_per_launch`), listed for comparison with the traffic.
+TRAFFIC_SERVING = {"sources_sha256": "5f4d2fc8d2507a1254c8cbd26b673928feb7636805e728a05a08dd1045ecabe6",
+                   "bytes_per_launch": 5206643662, "fetch_bytes_per_launch": 4170534195,
+                   "write_bytes_per_launch": 1036109467, "method_bytes_per_launch": 1968501468,
                    "queries": 512, "max_active": 512, "step_iters": 8}
 
 
@@ -577,13 +575,16 @@ def extra_workloads(F, W, args):
     avg_ms = rb["kernel_ms"] / launches
     per_launch = rb["alg_bytes"] / launches
     ach = per_launch / (avg_ms / 1e3) / 1e9
+    T = TRAFFIC_DEFAULT
+    traffic = T["bytes_per_launch"] if kernel_sources_sha256() == T["sources_sha256"] else None
     out["smartfl_batched"] = {
         "workload": "smartfl_200k_vars_500_layers_fwd_bwd_ranked, 512 queries per step (2% clamps each), fp32",
         "mups": round(rb["updates"] / rb["wall_s"], 1), "device_mups": round(rb["updates"] / (rb["kernel_ms"] / 1e3), 1),
         "ms_per_step": round(rb["wall_s"] * 1e3, 3), "p50_ms": pct(rb["lat_ms"], 50), "p99_ms": pct(rb["lat_ms"], 99),
         "iterations_p50": int(np.median(rb["iters"])),
         "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 5), "kernel": "k_persistent<PolLog32> (512 threads, 2 queries per CU)",
+                     "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "kernel": "k_persistent<PolLog32> (512 threads, 2 queries per CU)",
                      "launches": rb["launches"], "avg_launch_ms": round(avg_ms, 4), "method_bytes_per_launch": per_launch}}
     del rb
     torch.cuda.empty_cache()
