@@ -227,9 +227,10 @@ __device__ __forceinline__ void level_range(const DevGraph<typename P::S, typena
         const VarRecP pc0 = pr[0], pc1 = pr[1];
         if (v0 + tid < v1 && !stg) vr = vrec.ld(v0 + tid);
         S *const slots = stg ? s_slot : nullptr;
-        if (f0 + tid < f1) factor_rec<P, DAMP>(g, fr, acc, slots, b_slot);
+        // (the variable phase here rebuilds or stages beliefs, never reads (new, old) pairs)
+        if (f0 + tid < f1) factor_rec<P, DAMP, false>(g, fr, acc, slots, b_slot);
         for (int32_t i = f0 + tid + NT; i < f1; i += NT)
-            factor_rec<P, DAMP>(g, frec.ld(i), acc, slots, b_slot);
+            factor_rec<P, DAMP, false>(g, frec.ld(i), acc, slots, b_slot);
         if (TEAMS) {
             const GPtr<const int32_t> lst = plan.fac_list[FB_WAVE];
             int32_t o0 = plan.fac_lvl_off[FB_WAVE][L], o1 = plan.fac_lvl_off[FB_WAVE][L + 1];
@@ -620,7 +621,7 @@ struct fastlbp_graph {
     DevPool state;
     Belief *phi = nullptr, *bel = nullptr;
     void *msg = nullptr;
-    void *prev = nullptr;  // old values of written messages (plans with incremental variable tasks)
+    void *prev = nullptr;  // (new, old) pairs of written messages (plans with incremental variable tasks)
     RunState *st = nullptr;
     double *marg = nullptr;
     Launcher L;

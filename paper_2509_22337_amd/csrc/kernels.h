@@ -246,11 +246,20 @@ __device__ __forceinline__ typename P::S finish_msg(const DevGraph<typename P::S
     return l;
 }
 
-// Stores a new message, and its old value where the plan's variable tasks add new - old.
-template <class S, class V>
+// The (new, old) pair of a written message, side by side so that an incremental variable task
+// fetches both with one request.
+template <class S>
+struct alignas(2 * sizeof(S)) MsgPair {
+    S nw, od;
+};
+
+// Stores a new message, and the (new, old) pair where the plan's variable tasks add new - old
+// (PAIRS = false: the caller's variable phase never reads pairs, as in the single-workgroup level
+// loop, so the code for them is left out).
+template <class S, class V, bool PAIRS = true>
 __device__ __forceinline__ void put_msg(const DevGraph<S, V> &g, int32_t e, S nw, S old) {
     g.msg[e] = nw;
-    if (g.prev.p) g.prev[e] = old;
+    if (PAIRS && g.prev.p) GPtr<MsgPair<S>>((MsgPair<S> *)g.prev.p).st(e, MsgPair<S>{nw, old});
 }
 
 template <class P, bool DAMP>
@@ -730,7 +739,7 @@ __device__ __forceinline__ void stage_slot(typename P::S *slots, int32_t slot0, 
 // one the type's own formula gives.
 enum { FAM_OR = 0, FAM_IMPLIES = 1, FAM_NOISY = 2 };
 
-template <class P, bool DAMP, int D, int FAM>
+template <class P, bool DAMP, int D, int FAM, bool PAIRS>
 __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typename P::V> &g, int type, int32_t b,
                                              unsigned active, const Pair<typename P::V> &fp,
                                              const typename P::S (&lo)[D], const typename P::S (&vf)[D],
@@ -784,7 +793,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
             o1 = tmp;
         }
         const S l = finish_msg<P, DAMP>(g, lo[n], o0, o1, nnull > 0, acc);
-        put_msg(g, b + n, l, lo[n]);
+        put_msg<S, V, PAIRS>(g, b + n, l, lo[n]);
         stage_slot<P>(slots, slot0, active, n, l, lo[n]);
     }
     if (active & ((1u << n) - 1u)) {
@@ -836,7 +845,7 @@ __device__ __forceinline__ void factor_local(const DevGraph<typename P::S, typen
                 }
                 const int others_null = nnull - (nl[k] ? 1 : 0) + (nl[n] ? 1 : 0);
                 const S l = finish_msg<P, DAMP>(g, lo[k], o0, o1, others_null > 0, acc);
-                put_msg(g, b + k, l, lo[k]);
+                put_msg<S, V, PAIRS>(g, b + k, l, lo[k]);
                 stage_slot<P>(slots, slot0, active, k, l, lo[k]);
             }
             if (k >= 1 && k + 1 < n) run = combine<P>(run, lf[k]);
@@ -886,7 +895,7 @@ __device__ __forceinline__ void load_run(const S *p, S (&out)[N]) {
 // then the family's arithmetic. On a level staged in LDS, the belief of each written edge's
 // variable (as the factor read it, the value before the level) also goes to the edge's slot in
 // bslots, for the variable phase.
-template <class P, bool DAMP, int D>
+template <class P, bool DAMP, int D, bool PAIRS>
 __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::S, typename P::V> &g, int32_t b,
                                                      int type, int32_t fac, unsigned active, const int32_t *u,
                                                      Acc &acc, typename P::S *slots, Belief *bslots, int32_t slot0) {
@@ -918,28 +927,29 @@ __device__ __forceinline__ void factor_fetch_compute(const DevGraph<typename P::
             if ((active >> k) & 1u) bslots[slot0 + __builtin_popcount(active & ((1u << k) - 1u))] = B[k];
     }
     if (type == T_NOISY_OR)
-        factor_local<P, DAMP, D, FAM_NOISY>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+        factor_local<P, DAMP, D, FAM_NOISY, PAIRS>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
     else if (type == T_IMPLIES)
-        factor_local<P, DAMP, D, FAM_IMPLIES>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+        factor_local<P, DAMP, D, FAM_IMPLIES, PAIRS>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
     else
-        factor_local<P, DAMP, D, FAM_OR>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
+        factor_local<P, DAMP, D, FAM_OR, PAIRS>(g, type, b, active, fp, lo, vf, nl, ep, acc, slots, slot0);
 }
 
 // `slots`: the level's LDS staging area (persistent executor, staged levels), else nullptr.
-template <class P, bool DAMP>
+// PAIRS: keep the (new, old) pairs for incremental variable tasks when the plan has them.
+template <class P, bool DAMP, bool PAIRS = true>
 __device__ __forceinline__ void factor_rec(const DevGraph<typename P::S, typename P::V> &g, const FacRec &r, Acc &acc,
                                            typename P::S *slots = nullptr, Belief *bslots = nullptr) {
     const int d = r.meta & 0xff, type = (r.meta >> 8) & 0xff;
     const unsigned active = (unsigned)(r.meta >> 16) & 0xffu;
     const int32_t slot0 = r.u[8];
     switch (d) {
-    case 2: factor_fetch_compute<P, DAMP, 2>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 3: factor_fetch_compute<P, DAMP, 3>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 4: factor_fetch_compute<P, DAMP, 4>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 5: factor_fetch_compute<P, DAMP, 5>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 6: factor_fetch_compute<P, DAMP, 6>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 7: factor_fetch_compute<P, DAMP, 7>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
-    case 8: factor_fetch_compute<P, DAMP, 8>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 2: factor_fetch_compute<P, DAMP, 2, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 3: factor_fetch_compute<P, DAMP, 3, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 4: factor_fetch_compute<P, DAMP, 4, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 5: factor_fetch_compute<P, DAMP, 5, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 6: factor_fetch_compute<P, DAMP, 6, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 7: factor_fetch_compute<P, DAMP, 7, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
+    case 8: factor_fetch_compute<P, DAMP, 8, PAIRS>(g, r.b, type, r.fac, active, r.u, acc, slots, bslots, slot0); break;
     default: break;
     }
 }
@@ -988,7 +998,8 @@ __device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
 
 // Incremental variable task (LEVELS executor), from a record of the level's delta list: kind 0
 // rebuilds the belief from the whole row as var_rec does; kind 1 takes the belief before the level
-// and, for each message the level wrote, subtracts its old value (prev) and adds the new one. The
+// and, for each message the level wrote, subtracts its old value and adds the new one (both from the
+// message's (new, old) pair in prev). The
 // counts of infinite terms stay exact; the finite part is updated in float64 (beliefs are rebuilt
 // from the messages at the start of every run). Padding records (bit 30) store nothing.
 template <class P>
@@ -1002,23 +1013,20 @@ __device__ __forceinline__ void var_delta(const DevGraph<typename P::S, typename
     const int n = r.cnt & 0xffff;
     const bool pad = (r.cnt >> 30) & 1;
     Belief B = g.bel.ld(r.v);
-    S nw[kVarRecEdges], od[kVarRecEdges];
+    const GPtr<const MsgPair<S>> pairs((const MsgPair<S> *)g.prev.p);
+    MsgPair<S> m[kVarRecEdges];
 #pragma unroll
-    for (int j = 0; j < kVarRecEdges; ++j) {
-        const int32_t e = r.e[j < n ? j : 0];
-        nw[j] = g.msg[e];
-        od[j] = g.prev[e];
-    }
+    for (int j = 0; j < kVarRecEdges; ++j) m[j] = pairs.ld(r.e[j < n ? j : 0]);
 #pragma unroll
     for (int j = 0; j < kVarRecEdges; ++j)
         if (j < n) {
-            belief_sub<P>(B, od[j]);
-            belief_add<P>(B, nw[j]);
+            belief_sub<P>(B, m[j].od);
+            belief_add<P>(B, m[j].nw);
         }
     for (int32_t j = kVarRecEdges; j < n; ++j) {
-        const int32_t e = plan.dedge[r.start + j];
-        belief_sub<P>(B, g.prev[e]);
-        belief_add<P>(B, g.msg[e]);
+        const MsgPair<S> x = pairs.ld(plan.dedge[r.start + j]);
+        belief_sub<P>(B, x.od);
+        belief_add<P>(B, x.nw);
     }
     if (!pad) g.bel.st(r.v, B);
 }

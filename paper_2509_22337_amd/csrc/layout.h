@@ -132,8 +132,8 @@ struct DevGraph {
     GPtr<const Belief> phi;         // [V] priors + evidence
     GPtr<Belief> bel;               // [V]
     GPtr<S> msg;                    // [E]
-    GPtr<S> prev;                   // [E] value a written message had before the level (plans with
-                                    // incremental variable tasks), else null
+    GPtr<S> prev;                   // [2E] (new, old) of each message a level wrote, side by side
+                                    // (plans with incremental variable tasks), else null
     GPtr<const int32_t> edge_level; // [E] executed level of each edge (-1 for PRIOR edges)
     // weighted-term factors: term range per factor [F+1], weights in the value domain [T], start of
     // each factor's indicator rows [F+1], indicators (row t of factor a: one entry per edge, -1 any)

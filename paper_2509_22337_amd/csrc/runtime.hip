@@ -208,7 +208,7 @@ static void alloc_state(fastlbp_graph *g) {
     g->msg = g->state.get(mb);
     g->st = (RunState *)g->state.get(sizeof(RunState));
     g->marg = (double *)g->state.get(sizeof(double) * std::max(hg.V, 1));
-    g->prev = g->P->hp.has_delta ? g->state.get(mb) : nullptr;
+    g->prev = g->P->hp.has_delta ? g->state.get(2 * mb) : nullptr;  // (new, old) pairs
     HIPCHK(hipMemsetAsync(g->msg, 0, mb, g->L.stream));
     HIPCHK(hipMemsetAsync(g->bel, 0, sizeof(Belief) * std::max(hg.V, 1), g->L.stream));
     HIPCHK(hipMemsetAsync(g->st, 0, sizeof(RunState), g->L.stream));
@@ -691,7 +691,7 @@ int fastlbp_schedule_set(fastlbp_graph_t g, int32_t kind, const int32_t *edge_ra
         HIPCHK(hipStreamSynchronize(g->L.stream));
         auto P = make_plan(*g->S, g->alloc, g->L.stream, kind, edge_rank, g->pparams);
         if (P->hp.has_delta && !g->prev && g->resident) {  // old values for the incremental variable tasks
-            g->prev = g->state.get(g->S->msg_bytes() * std::max<int64_t>(g->hg().E, 1));
+            g->prev = g->state.get(2 * g->S->msg_bytes() * std::max<int64_t>(g->hg().E, 1));  // (new, old) pairs
             g->state_nominal = g->state.bytes;
         }
         g->drop_graph();
