@@ -563,6 +563,10 @@ struct Launcher {
     size_t hstatus_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t k0 = nullptr, k1 = nullptr;  // around the last persistent kernel
+    // a second stream for the workgroup-per-factor launch of a level, which then overlaps the
+    // level's other factor launches (fork and join through the two events)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     float last_kernel_ms = 0.f;
     void init(hipStream_t s, const Alloc &a) {
         pool.alloc = a;
@@ -576,6 +580,13 @@ struct Launcher {
         HIPCHK(hipEventCreate(&ev1));
         HIPCHK(hipEventCreate(&k0));
         HIPCHK(hipEventCreate(&k1));
+    }
+    // creates the side stream and its events on first need (never while a capture is open)
+    void ensure_side() {
+        if (side) return;
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     }
     void *descs(size_t bytes) {
         if (bytes > desc_cap) {
@@ -603,6 +614,12 @@ struct Launcher {
         if (ev1) (void)hipEventDestroy(ev1);
         if (k0) (void)hipEventDestroy(k0);
         if (k1) (void)hipEventDestroy(k1);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -756,7 +773,8 @@ static void launch_fused(fastlbp_graph *g, const DevGraph<typename PP::S, typena
 // One iteration of the LEVELS executor: for every level, the factor phase then the variable phase.
 // fuse (HYBRID executor): each run of narrow levels goes to one single-workgroup launch.
 template <class PP, bool ALL, bool DAMP>
-static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, bool fuse) {
+static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, typename PP::V> &dg, bool fuse,
+                              bool side_ok = true) {
     const HostPlan &pl = g->P->hp;
     const Plan &P = *g->P;
     hipStream_t s = g->L.stream;
@@ -768,6 +786,21 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
             continue;
         }
         int32_t o, n;
+        // the level's workgroup-per-factor tasks (few, long: a hub factor with thousands of inputs)
+        // run on the side stream beside its other factor launches; the variable phase waits for both
+        const int32_t ob = pl.fac_lvl_off[FB_BLOCK][L], nb = pl.fac_lvl_off[FB_BLOCK][L + 1] - ob;
+        const bool others = pl.frec_off[L + 1] > pl.frec_off[L] ||
+                            pl.fac_lvl_off[FB_WAVE][L + 1] > pl.fac_lvl_off[FB_WAVE][L] ||
+                            pl.fac_lvl_off[FB_TERMS_WAVE][L + 1] > pl.fac_lvl_off[FB_TERMS_WAVE][L] ||
+                            pl.trec_off[L + 1] > pl.trec_off[L];
+        const bool fork = nb > 0 && others && side_ok && g->L.side;
+        if (fork) {
+            HIPCHK(hipEventRecord(g->L.fork, s));
+            HIPCHK(hipStreamWaitEvent(g->L.side, g->L.fork, 0));
+            k_fac_block<PP, ALL, DAMP, block_threads<PP>()><<<std::min(nb, 4096), block_threads<PP>(), 0, g->L.side>>>(
+                dg, P.fac_list[FB_BLOCK] + ob, nb, L, g->st);
+            HIPCHK(hipEventRecord(g->L.join, g->L.side));
+        }
         o = pl.frec_off[L];
         n = pl.frec_off[L + 1] - o;
         if (n) k_fac_rec<PP, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, (const FacRec *)P.frec + o, n, g->st);
@@ -780,11 +813,11 @@ static void enqueue_iteration(fastlbp_graph *g, const DevGraph<typename PP::S, t
         o = pl.trec_off[L];
         n = pl.trec_off[L + 1] - o;
         if (n) k_fac_terms_rec<PP, DAMP><<<fac_grid(n, 256), 256, 0, s>>>(dg, (const TermRec *)P.trec + o, n, g->st);
-        o = pl.fac_lvl_off[FB_BLOCK][L];
-        n = pl.fac_lvl_off[FB_BLOCK][L + 1] - o;
-        if (n)
-            k_fac_block<PP, ALL, DAMP, block_threads<PP>()><<<std::min(n, 4096), block_threads<PP>(), 0, s>>>(
-                dg, P.fac_list[FB_BLOCK] + o, n, L, g->st);
+        if (fork)
+            HIPCHK(hipStreamWaitEvent(s, g->L.join, 0));
+        else if (nb)
+            k_fac_block<PP, ALL, DAMP, block_threads<PP>()><<<std::min(nb, 4096), block_threads<PP>(), 0, s>>>(
+                dg, P.fac_list[FB_BLOCK] + ob, nb, L, g->st);
         if (pl.has_delta && dg.prev.p) {  // incremental variable tasks
             o = pl.drec_off[L];
             n = pl.drec_off[L + 1] - o;
@@ -861,13 +894,15 @@ static void run_levels(fastlbp_graph *g, int32_t max_iters, double tol, double d
     int K = g->tune_graph_iters > 0 ? g->tune_graph_iters : std::max(1, std::min(32, 2048 / per_iter_kernels));
     K = std::min(K, max_iters);
     bool use_graph = g->opts.use_graph != 0 && !plain;
+    // (the allocation-free path keeps every launch on the caller's stream)
+    if (!plain && !g->P->hp.fac_list[FB_BLOCK].empty()) g->L.ensure_side();
     if (use_graph) ensure_iteration_graph<PP, ALL, DAMP>(g, dg, K, damping, fuse);
     int done_iters = 0;
     while (true) {
         if (use_graph)
             HIPCHK(hipGraphLaunch(g->gexec, s));
         else
-            for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg, fuse);
+            for (int k = 0; k < K; ++k) enqueue_iteration<PP, ALL, DAMP>(g, dg, fuse, !plain);
         HIPCHK(hipGetLastError());
         done_iters += K;
         if (done_iters >= max_iters) break;
@@ -972,6 +1007,7 @@ template <class PP, bool ALL, bool DAMP>
 static void step_levels_t(fastlbp_graph *g, double damping, int32_t iters) {
     auto dg = g->view<PP>(damping);
     hipStream_t s = g->L.stream;
+    if (!g->P->hp.fac_list[FB_BLOCK].empty()) g->L.ensure_side();
     HIPCHK(hipEventRecord(g->L.k0, s));
     launch_init_beliefs<PP>(g, dg);
     const bool fuse = choose_executor(g) == FASTLBP_EXEC_HYBRID;
