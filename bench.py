@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # about 4 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "5f4d2fc8d2507a1254c8cbd26b673928feb7636805e728a05a08dd1045ecabe6",
-                   "bytes_per_launch": 62408424395.7, "raw_bytes_per_launch": 43959077887.5,
+TRAFFIC_DEFAULT = {"sources_sha256": "a85447a8d9af2b48a28061f13e521c893d4191bb896a851b53b19c91c764968e",
+                   "bytes_per_launch": 65140916637.5, "raw_bytes_per_launch": 45340529906.7,
                    "queries": 512, "step_iters": 8}
 
 
@@ -51,9 +51,9 @@ TRAFFIC_DEFAULT = {"sources_sha256": "5f4d2fc8d2507a1254c8cbd26b673928feb7636805
 # x1.0, KiB per dispatch averaged over the profiled command's launches). A serving launch holds
 # whatever runs are in flight, so the profiled launches carried their own method bytes
 # (`method_bytes_per_launch`), listed for comparison with the traffic.
-TRAFFIC_SERVING = {"sources_sha256": "5f4d2fc8d2507a1254c8cbd26b673928feb7636805e728a05a08dd1045ecabe6",
-                   "bytes_per_launch": 5206643662, "fetch_bytes_per_launch": 4170534195,
-                   "write_bytes_per_launch": 1036109467, "method_bytes_per_launch": 1968501468,
+TRAFFIC_SERVING = {"sources_sha256": "a85447a8d9af2b48a28061f13e521c893d4191bb896a851b53b19c91c764968e",
+                   "bytes_per_launch": 5193337956, "fetch_bytes_per_launch": 4151315335,
+                   "write_bytes_per_launch": 1042022621, "method_bytes_per_launch": 1959302863,
                    "queries": 512, "max_active": 512, "step_iters": 8}
 
 
