@@ -424,6 +424,28 @@ def test_executors_and_graph_replay_agree(precision):
     assert a[2]["iterations"] == b[2]["iterations"]
 
 
+_SIDE_ORACLE = {}  # oracle marginals per schedule, shared by both precisions
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_side_stream_levels_graph_and_plain_agree(precision):
+    # levels holding workgroup-per-factor tasks beside thread tasks: the LEVELS executor runs the
+    # former on a second stream (inside the captured graph and in plain launches alike). Graph replay
+    # and plain launches must agree bit for bit and match the oracle, under flooding and under 8
+    # ordered groups (every level then has hub factors and thread factors)
+    for label, classes in (("flooding", 0), ("8 groups", 8)):
+        wk = W.bingo(3, num_tuples=20_000, num_rules=40_000, max_iters=6, ranked_classes=classes)
+        assert np.diff(wk.fac_off).max() > 257
+        a = _gpu_run(wk, precision, "levels", max_iters=6, tol=0.0, damping=0.0, use_graph=True)
+        b = _gpu_run(wk, precision, "levels", max_iters=6, tol=0.0, damping=0.0, use_graph=False)
+        if label not in _SIDE_ORACLE:
+            _SIDE_ORACLE[label] = oracle.bp(wk, 6, 0.0, 0.0)[0]
+        om = _SIDE_ORACLE[label]
+        _say("side stream", label, precision, "levels", int(a[3].max()) + 1, "err", np.abs(a[0] - om).max())
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
+        assert np.abs(a[0] - om).max() <= TOL[precision]
+
+
 def test_messages_roundtrip_and_reset():
     w = W.datalog(1)
     g = F.Graph.from_workload(w, precision="fp64")
