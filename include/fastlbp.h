@@ -448,7 +448,9 @@ typedef struct fastlbp_server_options {
                               per step = step_levels / levels per iteration, at least 1; wide runs
                               count kernel launches per iteration instead of levels), so a step costs
                               about the same for every run and small graphs finish in a few steps
-                              instead of waiting out the steps of large ones; 0: every run advances
+                              instead of waiting out the steps of large ones; after a step during
+                              which no request arrived (and none waits), the next step is 4 times
+                              longer, so runs left alone take fewer launches; 0: every run advances
                               by step_iters */
 } fastlbp_server_options;
 
@@ -473,7 +475,7 @@ typedef struct fastlbp_server_stats {
 } fastlbp_server_stats;
 
 /* Defaults: device 0, FP32, 256 active runs, 2 iterations per step (used when step_levels is 0),
- * budget 0 (80% of free), step_levels 4096. */
+ * budget 0 (80% of free), step_levels 2048. */
 void fastlbp_server_options_default(fastlbp_server_options *o);
 
 /* Starts a server with its own host thread and stream. Errors: E_INVALID_ARG, E_DEVICE. */

@@ -346,8 +346,12 @@ __global__ __launch_bounds__(NT) void k_persistent(const RunDesc<P> *descs, int3
     auto staged = [&](int32_t L) {
         return OFFL ? s_off[2 * (lds_levels + 1) + L] != 0 : (staging && plan.level_lds[L] != 0);
     };
-    for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
-    for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
+    // beliefs from the messages when the run starts; a later step of the same run continues from the
+    // beliefs the previous launch left, so a run's result does not depend on how it is cut into steps
+    if (st->iter == 0) {
+        for (int32_t i = tid; i < plan.init_var_count[VB_THREAD]; i += NT) var_thread<P>(g, plan.init_var[VB_THREAD][i]);
+        for (int32_t i = w; i < plan.init_var_count[VB_WAVE]; i += NW) var_wave<P>(g, plan.init_var[VB_WAVE][i], lane);
+    }
     if (tid == 0) {
         if (D.step > 0) st->step_end = st->iter + D.step;
         s_done = st->done || st->iter >= st->step_end;
@@ -1009,7 +1013,9 @@ static void step_levels_t(fastlbp_graph *g, double damping, int32_t iters) {
     hipStream_t s = g->L.stream;
     if (!g->P->hp.fac_list[FB_BLOCK].empty()) g->L.ensure_side();
     HIPCHK(hipEventRecord(g->L.k0, s));
-    launch_init_beliefs<PP>(g, dg);
+    // beliefs from the messages at the run's first step only (later steps continue from the
+    // beliefs the last one left, as one longer launch would)
+    if (g->h_state->iter == 0) launch_init_beliefs<PP>(g, dg);
     const bool fuse = choose_executor(g) == FASTLBP_EXEC_HYBRID;
     if (g->opts.use_graph) {
         ensure_iteration_graph<PP, ALL, DAMP>(g, dg, iters, damping, fuse);

@@ -999,9 +999,9 @@ __device__ __forceinline__ void belief_sub(Belief &B, typename P::S l) {
 // Incremental variable task (LEVELS executor), from a record of the level's delta list: kind 0
 // rebuilds the belief from the whole row as var_rec does; kind 1 takes the belief before the level
 // and, for each message the level wrote, subtracts its old value and adds the new one (both from the
-// message's (new, old) pair in prev). The
-// counts of infinite terms stay exact; the finite part is updated in float64 (beliefs are rebuilt
-// from the messages at the start of every run). Padding records (bit 30) store nothing.
+// message's (new, old) pair in prev). The counts of infinite terms stay exact; the finite part is
+// updated in float64 (beliefs are rebuilt from the messages at the start of every run). Padding
+// records (bit 30) store nothing.
 template <class P>
 __device__ __forceinline__ void var_delta(const DevGraph<typename P::S, typename P::V> &g, const DevPlan &plan,
                                           const VarRec &r) {
@@ -1034,8 +1034,8 @@ __device__ __forceinline__ void var_delta(const DevGraph<typename P::S, typename
 // Variable task of a staged level: its belief before the level (left in bslots by the factor that
 // wrote its first staged message) plus, for each message the level wrote, new minus old, read from
 // the staging slots. The variable phase thus reads LDS only. The counts of infinite terms stay
-// exact; the finite part is updated in float64 (the whole belief is rebuilt from the messages at
-// the start of every launch). A staged task has at least one written message (the host stages a
+// exact; the finite part is updated in float64 (the whole belief is rebuilt from the messages when
+// a run starts and before marginals are read). A staged task has at least one written message (the host stages a
 // level only then).
 template <class P>
 __device__ __forceinline__ void var_staged(const DevGraph<typename P::S, typename P::V> &g, const VarRecP &r,

@@ -38,6 +38,10 @@ using Clock = std::chrono::steady_clock;
 
 // Most iterations a wide run (LEVELS executor) advances per step when steps are sized in levels.
 constexpr int32_t kWideStepIters = 32;
+// Steps sized in levels grow by this factor while no request arrives: a request can only join at a
+// step's end, so short steps keep admission and retirement prompt while requests come in, and long
+// steps cut the launches (and host round trips) per iteration of the runs still going once they stop.
+constexpr int32_t kQuietStepFactor = 4;
 
 namespace {
 
@@ -70,6 +74,7 @@ struct fastlbp_server {
     std::unordered_set<fastlbp_graph *> managed;             // graphs submitted here (residency managed)
     uint64_t clock = 0;                                       // least-recently-used stamps
     uint64_t next_ticket = 1;
+    uint64_t submitted = 0;  // requests submitted so far
     bool stop = false;
     std::thread th;
     // statistics
@@ -127,11 +132,16 @@ void fastlbp_server::loop() {
     std::vector<fastlbp_graph *> gs, narrow, wide;
     std::vector<double> damp, narrow_damp;
     std::vector<int32_t> narrow_step, maxit;
+    // levels per step: step_levels, or kQuietStepFactor times more when no request arrived during
+    // the previous step and none waits
+    uint64_t seen = 0;
+    int64_t step_levels = opts.step_levels;
     // iterations a run advances per step: about step_levels levels (so a step costs about the same
     // for every run and small graphs are not held back by large ones), or step_iters
     auto iters_of = [&](int32_t units, int32_t max_iters) {
         if (opts.step_levels <= 0) return opts.step_iters;
-        return std::max<int32_t>(1, std::min<int32_t>(std::max<int32_t>(1, max_iters), opts.step_levels / std::max(1, units)));
+        const int64_t it = step_levels / std::max(1, units);
+        return int32_t(std::max<int64_t>(1, std::min<int64_t>(std::max<int32_t>(1, max_iters), it)));
     };
     while (true) {
         {
@@ -186,6 +196,9 @@ void fastlbp_server::loop() {
                 active.push_back(r);
             }
             peak_resident = std::max(peak_resident, resident_bytes());
+            const bool quiet = submitted == seen && pending.empty();
+            seen = submitted;
+            step_levels = int64_t(opts.step_levels) * (quiet ? kQuietStepFactor : 1);
             gs.clear();
             damp.clear();
             maxit.clear();
@@ -301,7 +314,7 @@ void fastlbp_server_options_default(fastlbp_server_options *o) {
     o->max_active = 256;
     o->step_iters = 2;
     o->memory_budget = 0;
-    o->step_levels = 4096;
+    o->step_levels = 2048;
 }
 
 int fastlbp_server_create(const fastlbp_server_options *opts, fastlbp_server_t *out) {
@@ -371,6 +384,7 @@ int fastlbp_server_submit(fastlbp_server_t s, fastlbp_graph_t g, int32_t n_ev, c
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        ++s->submitted;
         if (s->stop) {
             set_error("server is shutting down");
             return FASTLBP_E_STATE;
