@@ -38,11 +38,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # Measured HBM traffic of one k_persistent launch of the batched SmartFL-shaped queries (512 queries,
-# about 4 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
+# 2 to 8 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "a85447a8d9af2b48a28061f13e521c893d4191bb896a851b53b19c91c764968e",
-                   "bytes_per_launch": 65140916637.5, "raw_bytes_per_launch": 45340529906.7,
+TRAFFIC_DEFAULT = {"sources_sha256": "048b815afe0b400a353d73b627decf42a84adf5887fc595c87ddc6ec309d1d14",
+                   "bytes_per_launch": 119551832786.9, "raw_bytes_per_launch": 83613429222.0,
                    "queries": 512, "step_iters": 8}
 
 
@@ -51,9 +51,9 @@ TRAFFIC_DEFAULT = {"sources_sha256": "a85447a8d9af2b48a28061f13e521c893d4191bb89
 # x1.0, KiB per dispatch averaged over the profiled command's launches). A serving launch holds
 # whatever runs are in flight, so the profiled launches carried their own method bytes
 # (`method_bytes_per_launch`), listed for comparison with the traffic.
-TRAFFIC_SERVING = {"sources_sha256": "a85447a8d9af2b48a28061f13e521c893d4191bb896a851b53b19c91c764968e",
-                   "bytes_per_launch": 5193337956, "fetch_bytes_per_launch": 4151315335,
-                   "write_bytes_per_launch": 1042022621, "method_bytes_per_launch": 1959302863,
+TRAFFIC_SERVING = {"sources_sha256": "048b815afe0b400a353d73b627decf42a84adf5887fc595c87ddc6ec309d1d14",
+                   "bytes_per_launch": 9097949705, "fetch_bytes_per_launch": 7396783433,
+                   "write_bytes_per_launch": 1701166271, "method_bytes_per_launch": 3811734660,
                    "queries": 512, "max_active": 512, "step_iters": 8}
 
 
