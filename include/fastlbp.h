@@ -449,8 +449,8 @@ typedef struct fastlbp_server_options {
                               count kernel launches per iteration instead of levels), so a step costs
                               about the same for every run and small graphs finish in a few steps
                               instead of waiting out the steps of large ones; after a step during
-                              which no request arrived (and none waits), the next step is 4 times
-                              longer, so runs left alone take fewer launches; 0: every run advances
+                              which no request arrived (and none waits), the next step of the
+                              narrow runs is 4 times longer, so runs left alone take fewer launches; 0: every run advances
                               by step_iters */
 } fastlbp_server_options;
 

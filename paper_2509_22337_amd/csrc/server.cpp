@@ -132,15 +132,16 @@ void fastlbp_server::loop() {
     std::vector<fastlbp_graph *> gs, narrow, wide;
     std::vector<double> damp, narrow_damp;
     std::vector<int32_t> narrow_step, maxit;
-    // levels per step: step_levels, or kQuietStepFactor times more when no request arrived during
-    // the previous step and none waits
+    // levels per step of the narrow runs: step_levels, or kQuietStepFactor times more when no
+    // request arrived during the previous step and none waits (wide runs keep step_levels: each
+    // captures its step's iterations in a hipGraph, which a changing step length would re-capture)
     uint64_t seen = 0;
     int64_t step_levels = opts.step_levels;
-    // iterations a run advances per step: about step_levels levels (so a step costs about the same
-    // for every run and small graphs are not held back by large ones), or step_iters
-    auto iters_of = [&](int32_t units, int32_t max_iters) {
+    // iterations a run advances per step: about `levels` levels (so a step costs about the same for
+    // every run and small graphs are not held back by large ones), or step_iters
+    auto iters_of = [&](int64_t levels, int32_t units, int32_t max_iters) {
         if (opts.step_levels <= 0) return opts.step_iters;
-        const int64_t it = step_levels / std::max(1, units);
+        const int64_t it = levels / std::max(1, units);
         return int32_t(std::max<int64_t>(1, std::min<int64_t>(std::max<int32_t>(1, max_iters), it)));
     };
     while (true) {
@@ -227,11 +228,11 @@ void fastlbp_server::loop() {
                     wide.push_back(gs[i]);
                     // (at most kWideStepIters: each handle captures its step's iterations in a hipGraph)
                     step_levels_enqueue(gs[i], damp[i],
-                                        std::min(kWideStepIters, iters_of(graph_launches_per_iter(gs[i]), maxit[i])));
+                                        std::min(kWideStepIters, iters_of(opts.step_levels, graph_launches_per_iter(gs[i]), maxit[i])));
                 } else {
                     narrow.push_back(gs[i]);
                     narrow_damp.push_back(damp[i]);
-                    narrow_step.push_back(iters_of(graph_exec_levels(gs[i]), maxit[i]));
+                    narrow_step.push_back(iters_of(step_levels, graph_exec_levels(gs[i]), maxit[i]));
                 }
             }
             if (!narrow.empty()) {
