@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # 2 to 8 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "048b815afe0b400a353d73b627decf42a84adf5887fc595c87ddc6ec309d1d14",
-                   "bytes_per_launch": 119551832786.9, "raw_bytes_per_launch": 83613429222.0,
+TRAFFIC_DEFAULT = {"sources_sha256": "442899f32a989fc30eea1904d8870beae6e45f92c395688bb012c13c61748faf",
+                   "bytes_per_launch": 119981002914.9, "raw_bytes_per_launch": 83863155924.5,
                    "queries": 512, "step_iters": 8}
 
 
@@ -51,9 +51,9 @@ TRAFFIC_DEFAULT = {"sources_sha256": "048b815afe0b400a353d73b627decf42a84adf5887
 # x1.0, KiB per dispatch averaged over the profiled command's launches). A serving launch holds
 # whatever runs are in flight, so the profiled launches carried their own method bytes
 # (`method_bytes_per_launch`), listed for comparison with the traffic.
-TRAFFIC_SERVING = {"sources_sha256": "048b815afe0b400a353d73b627decf42a84adf5887fc595c87ddc6ec309d1d14",
-                   "bytes_per_launch": 9097949705, "fetch_bytes_per_launch": 7396783433,
-                   "write_bytes_per_launch": 1701166271, "method_bytes_per_launch": 3811734660,
+TRAFFIC_SERVING = {"sources_sha256": "442899f32a989fc30eea1904d8870beae6e45f92c395688bb012c13c61748faf",
+                   "bytes_per_launch": 9273922123, "fetch_bytes_per_launch": 7464826895,
+                   "write_bytes_per_launch": 1809095228, "method_bytes_per_launch": 3846704703,
                    "queries": 512, "max_active": 512, "step_iters": 8}
 
 
