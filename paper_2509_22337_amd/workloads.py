@@ -357,6 +357,8 @@ def _power_law_counts(rng, total: int, alpha: float, kmax: int) -> np.ndarray:
     pk /= pk.sum()
     mean = float((k * pk).sum())
     counts = rng.choice(np.arange(1, kmax + 1), size=int(total / mean * 1.1) + 16, p=pk)
+    while counts.sum() < total:  # (rare at small totals: a short draw) draw more
+        counts = np.concatenate([counts, rng.choice(np.arange(1, kmax + 1), size=int(total / mean * 0.5) + 16, p=pk)])
     cs = np.cumsum(counts)
     n = int(np.searchsorted(cs, total)) + 1
     counts = counts[:n].copy()
