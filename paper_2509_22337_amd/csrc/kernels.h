@@ -407,32 +407,56 @@ struct TeamScan {
     }
 };
 
-// Reads input i of factor (b, d): its old message, its v->f message and its leaf.
-template <class P>
-__device__ __forceinline__ HF<typename P::V> load_leaf(const DevGraph<typename P::S, typename P::V> &g, int type,
-                                                       int32_t e, typename P::S &old, bool &null) {
+// The leaves of SB consecutive inputs of a factor (positions i0 + k0 .. of the edge range starting at
+// b, those before i1 valid), with every load issued before any is used: positions past the chunk
+// load the lane's first edge instead (b + i0 <= the head edge, always valid) and are masked. ok[j]
+// marks the valid positions; x[j] is the identity leaf where a position is invalid or its v->f
+// message is null.
+template <class P, int SB, int CMAX>
+__device__ __forceinline__ void load_leaves(const DevGraph<typename P::S, typename P::V> &g, int type, int32_t b,
+                                            int32_t i0, int32_t i1, int k0, HF<typename P::V> (&x)[SB],
+                                            typename P::S (&o)[SB], bool (&nl)[SB], bool (&ok)[SB]) {
     using V = typename P::V;
-    old = g.msg[e];
-    typename P::S vf = v2f<P>(g.bel.ld(g.edge_var[e]), old, null);
-    if (null) return identity<P>();
-    V m0, m1;
-    P::leaf(vf, m0, m1);
-    Pair<V> ep = {P::zero(), P::one()};
-    if (type == T_NOISY_OR) ep = g.epar.ld(e);
-    return make_leaf<P>(type, m0, m1, ep);
+    int32_t v[SB];
+    Pair<V> ep[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+        ok[j] = (k0 + j < CMAX) && (i0 + k0 + j < i1);
+        const int32_t e = b + (ok[j] ? i0 + k0 + j : i0);
+        o[j] = g.msg[e];
+        v[j] = g.edge_var[e];
+        ep[j] = {P::zero(), P::one()};
+        if (type == T_NOISY_OR) ep[j] = g.epar.ld(e);
+    }
+    Belief B[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) B[j] = g.bel.ld(v[j]);
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+        bool n;
+        const typename P::S vf = v2f<P>(B[j], o[j], n);
+        V m0, m1;
+        P::leaf(vf, m0, m1);
+        const HF<V> t = make_leaf<P>(type, m0, m1, ep[j]);
+        nl[j] = ok[j] && n;
+        const bool id = !ok[j] || n;
+        x[j].h = id ? P::one() : t.h;
+        x[j].f = id ? P::zero() : t.f;
+    }
 }
 
-// Writes the messages of the head and of every active input of factor a. TEAM = 1 keeps the
-// leaves of its (at most CMAX) inputs in registers. A team splits each lane's chunk into sub-chunks
-// of 4 and re-reads leaves (cache hits) instead of holding them, so that a 1024-lane workgroup stays
-// within its 128-register budget in float64 without spilling.
+// Writes the messages of the head and of every active input of factor a, NT lanes working together:
+// each lane owns a chunk of at most CMAX consecutive inputs, taken in sub-chunks of 4 whose loads are
+// issued together. A first pass combines each sub-chunk; the scan across the lanes gives the prefix
+// before and the suffix after each lane's chunk; a second pass, over the sub-chunks from last to
+// first, reloads each sub-chunk (cache hits) and forms its suffix and exclusive products. Leaves are
+// reloaded instead of held so that a 1024-lane workgroup stays within its 128-register budget.
 template <class P, int TEAM, int CMAX, bool ALL_ACTIVE, bool DAMP>
 __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typename P::V> &g, int32_t a, int lane, int level,
                             Acc &acc, TeamLds<typename P::V> *lds) {
     using S = typename P::S;
     using V = typename P::V;
-    constexpr bool KEEP = (TEAM == 1);
-    constexpr int SB = KEEP ? CMAX : 4;         // sub-chunk length
+    constexpr int SB = 4;                       // sub-chunk length
     constexpr int NS = (CMAX + SB - 1) / SB;    // sub-chunks per lane
     const int32_t b = g.fac_off[a];
     const int32_t d = g.fac_off[a + 1] - b;
@@ -453,28 +477,20 @@ __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typena
     // chunk of inputs owned by this lane
     const int32_t c = (n + TEAM - 1) / TEAM;
     const int32_t i0 = min(n, lane * c), i1 = min(n, i0 + c);
-    HF<V> lf[KEEP ? CMAX : 1];
-    S lo[KEEP ? CMAX : 1];
-    bool ln[KEEP ? CMAX : 1];
     HF<V> sub[NS];  // aggregate of each sub-chunk, later the prefix before it
     int nnull = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sub[s] = identity<P>();
+        if (i0 + s * SB < i1) {
+            HF<V> x[SB];
+            S o[SB];
+            bool nl[SB], ok[SB];
+            load_leaves<P, SB, CMAX>(g, type, b, i0, i1, s * SB, x, o, nl, ok);
 #pragma unroll
-        for (int j = 0; j < SB; ++j) {
-            const int k = s * SB + j;
-            if (k < CMAX && i0 + k < i1) {
-                S o;
-                bool nl;
-                HF<V> x = load_leaf<P>(g, type, b + i0 + k, o, nl);
-                if (KEEP) {
-                    lf[KEEP ? k : 0] = x;
-                    lo[KEEP ? k : 0] = o;
-                    ln[KEEP ? k : 0] = nl;
-                }
-                nnull += nl ? 1 : 0;
-                sub[s] = combine<P>(sub[s], x);
+            for (int j = 0; j < SB; ++j) {
+                nnull += nl[j] ? 1 : 0;
+                if (ok[j]) sub[s] = combine<P>(sub[s], x[j]);
             }
         }
     }
@@ -505,51 +521,34 @@ __device__ __forceinline__ void factor_team(const DevGraph<typename P::S, typena
     HF<V> rsuf = suf;
 #pragma unroll
     for (int s = NS - 1; s >= 0; --s) {
+        if (i0 + s * SB >= i1) continue;
+        HF<V> x[SB];
+        S o[SB];
+        bool nl[SB], ok[SB];
+        load_leaves<P, SB, CMAX>(g, type, b, i0, i1, s * SB, x, o, nl, ok);
         HF<V> sx[SB];
         HF<V> run = rsuf;
 #pragma unroll
         for (int j = SB - 1; j >= 0; --j) {
-            const int k = s * SB + j;
-            if (k < CMAX && i0 + k < i1) {
-                sx[j] = run;
-                HF<V> x;
-                if (KEEP) {
-                    x = lf[KEEP ? k : 0];
-                } else {
-                    S o;
-                    bool nl;
-                    x = load_leaf<P>(g, type, b + i0 + k, o, nl);
-                }
-                run = combine<P>(x, run);
-            }
+            sx[j] = run;
+            if (ok[j]) run = combine<P>(x[j], run);
         }
         rsuf = run;
         run = sub[s];
 #pragma unroll
         for (int j = 0; j < SB; ++j) {
-            const int k = s * SB + j;
-            if (k < CMAX && i0 + k < i1) {
-                const int32_t e = b + i0 + k;
-                S o;
-                bool nl;
-                HF<V> x;
-                if (KEEP) {
-                    x = lf[KEEP ? k : 0];
-                    o = lo[KEEP ? k : 0];
-                    nl = ln[KEEP ? k : 0];
-                } else {
-                    x = load_leaf<P>(g, type, e, o, nl);
-                }
+            if (ok[j]) {
+                const int32_t e = b + i0 + s * SB + j;
                 if (is_active<ALL_ACTIVE>(g.edge_level, e, level)) {
                     HF<V> xo = combine<P>(run, sx[j]);
                     Pair<V> ep = {P::zero(), P::one()};
                     if (type == T_NOISY_OR) ep = g.epar.ld(e);
                     V o0, o1;
                     input_msg<P>(type, xo, my0, my1, fp, ep, o0, o1);
-                    int others_null = ntot - (nl ? 1 : 0) + (null_h ? 1 : 0);
-                    store_msg<P, DAMP>(g, e, o, o0, o1, others_null > 0, acc);
+                    int others_null = ntot - (nl[j] ? 1 : 0) + (null_h ? 1 : 0);
+                    store_msg<P, DAMP>(g, e, o[j], o0, o1, others_null > 0, acc);
                 }
-                run = combine<P>(run, x);
+                run = combine<P>(run, x[j]);
             }
         }
     }
