@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # 2 to 8 iterations per launch), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings
 # (profiles/k_persistent_smartfl_200k_batch512.md). Valid only for the kernel sources it was taken
 # with: any change to them makes the reported traffic null until it is measured again.
-TRAFFIC_DEFAULT = {"sources_sha256": "442899f32a989fc30eea1904d8870beae6e45f92c395688bb012c13c61748faf",
-                   "bytes_per_launch": 119981002914.9, "raw_bytes_per_launch": 83863155924.5,
+TRAFFIC_DEFAULT = {"sources_sha256": "098c65e4dd32525c03fb8cb86ef94d48dae4b6352ded41a05be0ec1bb39a436d",
+                   "bytes_per_launch": 119237182021.0, "raw_bytes_per_launch": 83470086135.5,
                    "queries": 512, "step_iters": 8}
 
 
@@ -51,9 +51,9 @@ TRAFFIC_DEFAULT = {"sources_sha256": "442899f32a989fc30eea1904d8870beae6e45f92c3
 # x1.0, KiB per dispatch averaged over the profiled command's launches). A serving launch holds
 # whatever runs are in flight, so the profiled launches carried their own method bytes
 # (`method_bytes_per_launch`), listed for comparison with the traffic.
-TRAFFIC_SERVING = {"sources_sha256": "442899f32a989fc30eea1904d8870beae6e45f92c395688bb012c13c61748faf",
-                   "bytes_per_launch": 9273922123, "fetch_bytes_per_launch": 7464826895,
-                   "write_bytes_per_launch": 1809095228, "method_bytes_per_launch": 3846704703,
+TRAFFIC_SERVING = {"sources_sha256": "098c65e4dd32525c03fb8cb86ef94d48dae4b6352ded41a05be0ec1bb39a436d",
+                   "bytes_per_launch": 9051213802, "fetch_bytes_per_launch": 7395182754,
+                   "write_bytes_per_launch": 1656031049, "method_bytes_per_launch": 3811734660,
                    "queries": 512, "max_active": 512, "step_iters": 8}
 
 
