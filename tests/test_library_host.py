@@ -145,3 +145,18 @@ def test_graph_create_reports_missing_device():
     with pytest.raises(F.FastLBPError) as ei:
         F.Graph.from_workload(w)
     assert ei.value.code == F.E_DEVICE
+
+
+@pytest.mark.parametrize("scale", [1 / 500, 1 / 2000, 1 / 5000])
+def test_bingo_generator_at_small_scales(scale):
+    # the power-law fan-in draw must cover the rule count even when a short draw falls below it;
+    # every head's noisy-OR factor then has its rules plus the head, and the graph validates
+    w = W.config("C5", seed=0, scale=scale)
+    nt, nr = w.meta["num_tuples"], w.meta["num_rules"]
+    deg = np.diff(w.fac_off)
+    no = w.fac_type == W.NOISY_OR
+    assert int((deg[no] - 1).sum()) == nr
+    assert int((w.fac_type == W.AND).sum()) == nr
+    assert deg[no].max() - 1 <= 10_000
+    assert w.num_vars == nt + nr
+    assert _codes(w) == F.OK
